@@ -1,0 +1,206 @@
+"""CPU FP64 oracle for the two-electron TDA-TDDFT gradient (test infrastructure).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  It wraps ``liboracle.so`` (built from ``tdg_oracle.c`` with gcc,
+OpenMP, plain scalar code) through ctypes and shares no code with the HIP
+library.  See ``tdg_oracle.c`` for what is computed and which passages of the
+paper each piece follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tdg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc -O2 -fopenmp (plain C, no intrinsics)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-D_DEFAULT_SOURCE", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Basis(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("coords", C.c_void_p),
+                ("n_shells", C.c_int32), ("shell_atom", C.c_void_p), ("shell_l", C.c_void_p),
+                ("shell_nprim", C.c_void_p), ("shell_prim_off", C.c_void_p),
+                ("shell_ao_off", C.c_void_p),
+                ("n_prims", C.c_int32), ("exps", C.c_void_p), ("coefs", C.c_void_p),
+                ("n_bf", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("omega", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
+                ("tau", C.c_double), ("terms", C.c_int32), ("nthreads", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("quartets", C.c_int64), ("prim_quartets", C.c_int64),
+                ("skipped", C.c_int64), ("one_center", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        vp, i64 = C.c_void_p, C.c_int64
+        L.orc_grad.argtypes = [C.POINTER(Basis), vp, vp, vp, C.POINTER(Params), vp, C.POINTER(Stats)]
+        L.orc_grad_brute.argtypes = [C.POINTER(Basis), vp, vp, vp, C.POINTER(Params), vp]
+        L.orc_energy.argtypes = [C.POINTER(Basis), vp, vp, vp, C.POINTER(Params), vp]
+        L.orc_quartet_contribs.argtypes = [C.POINTER(Basis), vp, vp, vp, C.POINTER(Params), i64, vp, vp]
+        L.orc_quartet_bounds.argtypes = [C.POINTER(Basis), vp, vp, vp, i64, vp, vp]
+        L.orc_schwarz.argtypes = [C.POINTER(Basis), vp]
+        L.orc_eri_tensor.argtypes = [C.POINTER(Basis), C.c_int, C.c_double, vp]
+        L.orc_norm_coefs.argtypes = [C.POINTER(Basis), vp]
+        L.orc_prim_eri.argtypes = [vp, vp, vp, C.c_int, C.c_double]
+        L.orc_prim_eri.restype = C.c_double
+        L.orc_boys.argtypes = [C.c_int, C.c_double, vp]
+        for f in ("orc_grad", "orc_grad_brute", "orc_energy", "orc_quartet_contribs",
+                  "orc_quartet_bounds", "orc_schwarz", "orc_eri_tensor", "orc_norm_coefs"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class _Bound:
+    """Keeps the numpy arrays behind a Basis struct alive."""
+
+    def __init__(self, mol, coords=None):
+        c = np.ascontiguousarray(mol.coords if coords is None else coords, dtype=np.float64)
+        self.keep = [c, mol.shell_atom, mol.shell_l, mol.shell_nprim, mol.shell_prim_off,
+                     mol.shell_ao_off, mol.exps, mol.coefs]
+        self.b = Basis(mol.n_atoms, _p(c).value, mol.n_shells, _p(mol.shell_atom).value,
+                       _p(mol.shell_l).value, _p(mol.shell_nprim).value,
+                       _p(mol.shell_prim_off).value, _p(mol.shell_ao_off).value,
+                       mol.n_prims, _p(mol.exps).value, _p(mol.coefs).value, mol.n_bf)
+
+
+def _params(mol, tau=0.0, terms=7, nthreads=0, omega=None, alpha=None, beta=None):
+    return Params(mol.omega if omega is None else omega, mol.alpha if alpha is None else alpha,
+                  mol.beta if beta is None else beta, tau, terms, nthreads)
+
+
+def _dens(mol, P0=None, PD=None, R=None):
+    f = lambda x, d: np.ascontiguousarray(d if x is None else x, dtype=np.float64)
+    return f(P0, mol.P0), f(PD, mol.PD), f(R, mol.R)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with status {rc}")
+
+
+def grad(mol, tau=0.0, terms=7, nthreads=0, coords=None, P0=None, PD=None, R=None,
+         omega=None, alpha=None, beta=None, return_stats=False):
+    """Gradient [n_atoms, 3] (hartree/bohr), unique quartets with symmetrised Gamma."""
+    bb = _Bound(mol, coords)
+    P0, PD, R = _dens(mol, P0, PD, R)
+    prm = _params(mol, tau, terms, nthreads, omega, alpha, beta)
+    out = np.zeros((mol.n_atoms, 3))
+    st = Stats()
+    _check(lib().orc_grad(C.byref(bb.b), _p(P0), _p(PD), _p(R), C.byref(prm), _p(out), C.byref(st)),
+           "grad")
+    if return_stats:
+        return out, {"quartets": st.quartets, "prim_quartets": st.prim_quartets,
+                     "skipped": st.skipped, "one_center": st.one_center}
+    return out
+
+
+def grad_brute(mol, terms=7, nthreads=0, P0=None, PD=None, R=None, omega=None, alpha=None,
+               beta=None):
+    """Gradient over every ordered shell quartet with the literal Gamma (tiny bases)."""
+    bb = _Bound(mol)
+    P0, PD, R = _dens(mol, P0, PD, R)
+    prm = _params(mol, 0.0, terms, nthreads, omega, alpha, beta)
+    out = np.zeros((mol.n_atoms, 3))
+    _check(lib().orc_grad_brute(C.byref(bb.b), _p(P0), _p(PD), _p(R), C.byref(prm), _p(out)),
+           "grad_brute")
+    return out
+
+
+def energy(mol, terms=7, nthreads=0, coords=None, P0=None, PD=None, R=None, omega=None,
+           alpha=None, beta=None):
+    """Pseudo-energy sum Gamma (mu nu|lam sig) + Gamma^lr (mu nu|lam sig)_lr."""
+    bb = _Bound(mol, coords)
+    P0, PD, R = _dens(mol, P0, PD, R)
+    prm = _params(mol, 0.0, terms, nthreads, omega, alpha, beta)
+    e = np.zeros(1)
+    _check(lib().orc_energy(C.byref(bb.b), _p(P0), _p(PD), _p(R), C.byref(prm), _p(e)), "energy")
+    return float(e[0])
+
+
+def quartet_contribs(mol, quartets, terms=7, nthreads=0):
+    """Per-quartet contributions [nq, 4, 3] for shell quartets given as [nq, 4] int32."""
+    bb = _Bound(mol)
+    P0, PD, R = _dens(mol)
+    q = np.ascontiguousarray(quartets, dtype=np.int32)
+    out = np.zeros((q.shape[0], 4, 3))
+    prm = _params(mol, 0.0, terms, nthreads)
+    _check(lib().orc_quartet_contribs(C.byref(bb.b), _p(P0), _p(PD), _p(R), C.byref(prm),
+                                      q.shape[0], _p(q), _p(out)), "quartet_contribs")
+    return out
+
+
+def quartet_bounds(mol, quartets):
+    bb = _Bound(mol)
+    P0, PD, R = _dens(mol)
+    q = np.ascontiguousarray(quartets, dtype=np.int32)
+    out = np.zeros(q.shape[0])
+    _check(lib().orc_quartet_bounds(C.byref(bb.b), _p(P0), _p(PD), _p(R), q.shape[0], _p(q),
+                                    _p(out)), "quartet_bounds")
+    return out
+
+
+def schwarz(mol):
+    bb = _Bound(mol)
+    ns = mol.n_shells
+    out = np.zeros(ns * (ns + 1) // 2)
+    _check(lib().orc_schwarz(C.byref(bb.b), _p(out)), "schwarz")
+    return out
+
+
+def eri_tensor(mol, op=0, omega=None):
+    bb = _Bound(mol)
+    n = mol.n_bf
+    out = np.zeros((n, n, n, n))
+    _check(lib().orc_eri_tensor(C.byref(bb.b), op, mol.omega if omega is None else omega,
+                                _p(out)), "eri_tensor")
+    return out
+
+
+def norm_coefs(mol):
+    bb = _Bound(mol)
+    out = np.zeros(mol.n_prims)
+    _check(lib().orc_norm_coefs(C.byref(bb.b), _p(out)), "norm_coefs")
+    return out
+
+
+def prim_eri(lxyz, zeta, centers, op=0, omega=0.3):
+    l = np.ascontiguousarray(lxyz, dtype=np.int32).reshape(4, 3)
+    z = np.ascontiguousarray(zeta, dtype=np.float64).reshape(4)
+    c = np.ascontiguousarray(centers, dtype=np.float64).reshape(4, 3)
+    return float(lib().orc_prim_eri(_p(l), _p(z), _p(c), op, omega))
+
+
+def boys(mmax, T):
+    out = np.zeros(mmax + 1)
+    lib().orc_boys(mmax, float(T), _p(out))
+    return out
