@@ -1,0 +1,157 @@
+"""Benchmark: two-electron TDA-TDDFT gradient (ERI-derivative J/K part) on one MI355X.
+
+Workload: the 60-atom alkane-like chain (20 heavy + 40 H atoms, 500 Cartesian
+functions, l <= 2, contraction degrees up to 6), seeded synthetic densities,
+omega = 0.3, alpha = 0.157706, beta = 0.842294, density-multiplied Schwarz
+threshold 1e-10, all terms (J, full-range K, long-range K), FP64.
+
+One step = one call of the library's gradient entry point with the densities
+already resident in device memory: density preparation, screening and task
+generation, all 21 ERI-derivative class kernels and the per-atom reduction.
+
+Prints one JSON line (see README/DESIGN for the fields).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ERI-deriv quartets/s & J/K-grad wall s, mixed vs FP64 on 1 GPU @1e-6 Eh/bohr"
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def cpu_baseline(mol, target_s=15.0, seed=7):
+    """The oracle, untuned, on a bounded random sample of the workload's surviving quartets
+    (drawn uniformly from the unique shell quartets and kept when the oracle's own
+    density-multiplied Schwarz bound passes), all host threads."""
+    import numpy as np
+
+    import oracle
+    oracle.build(force=False)
+    rng = np.random.default_rng(seed)
+    ns = mol.n_shells
+    a = np.arange(ns)
+    pa = np.concatenate([np.full(i + 1, i) for i in range(ns)])
+    pb = np.concatenate([a[: i + 1] for i in range(ns)])
+    npair = len(pa)
+    atom = mol.shell_atom
+    nthreads = os.cpu_count() or 1
+
+    def draw(nsurv):
+        out, have = [], 0
+        while have < nsurv:
+            i = rng.integers(0, npair, 8_000_000)
+            j = rng.integers(0, npair, 8_000_000)
+            hi, lo = np.maximum(i, j), np.minimum(i, j)
+            q = np.stack([pa[hi], pb[hi], pa[lo], pb[lo]], 1).astype(np.int32)
+            one = (atom[q[:, 0]] == atom[q[:, 1]]) & (atom[q[:, 1]] == atom[q[:, 2]]) & (atom[q[:, 2]] == atom[q[:, 3]])
+            q = q[~one]
+            q = q[oracle.quartet_bounds(mol, q) >= 1e-10]
+            out.append(q)
+            have += len(q)
+        return np.concatenate(out)[:nsurv]
+
+    probe = draw(4000)
+    t = time.perf_counter()
+    oracle.quartet_contribs(mol, probe, nthreads=nthreads)
+    rate = len(probe) / (time.perf_counter() - t)
+    n = int(min(3_000_000, max(4000, rate * target_s)))
+    sample = draw(n)
+    t = time.perf_counter()
+    oracle.quartet_contribs(mol, sample, nthreads=nthreads)
+    dt = time.perf_counter() - t
+    return {"value": n / dt, "unit": "quartets/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{n} surviving shell quartets drawn uniformly from the workload's unique "
+                      f"quartets (oracle's own screening at 1e-10), {dt:.1f} s on {nthreads} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md and not run here", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2407_16586_amd import synth, tdgrad
+    from paper_2407_16586_amd.workmodel import FLOPS_PER_PRIM
+
+    mol = synth.config1()
+    dev = torch.device("cuda:0")
+    print(f"bench: plan for {mol.name}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    plan = tdgrad.Plan(mol, schwarz_tol=1e-10)
+    plan_s = time.perf_counter() - t0
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    P0, PD, R = t(mol.P0), t(mol.PD), t(mol.R)
+    out = torch.zeros((mol.n_atoms, 3), dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        plan.grad_device(P0, PD, R, out, stats=True)
+    torch.cuda.synchronize()
+    print("bench: warmup done", file=sys.stderr, flush=True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(plan.grad_device(P0, PD, R, out, stats=True))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = 1e3 * dt / args.steps
+    st = stats[-1]
+    quartets = st["quartets"]
+    class_ms = np.mean([s["class_ms"] for s in stats], axis=0)
+    prims = np.array(st["class_prim_quartets"], dtype=np.float64)
+    flops = np.array([FLOPS_PER_PRIM[c] for c in tdgrad.CLASSES], dtype=np.float64) * prims
+    dom = int(np.argmax(class_ms))
+    achieved = flops[dom] / (class_ms[dom] * 1e-3) / 1e12
+    all_tflops = flops.sum() / (class_ms.sum() * 1e-3) / 1e12
+    rec = {
+        "metric": METRIC,
+        "value": quartets / (ms_step * 1e-3),
+        "unit": "quartets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "60-atom alkane-like chain, 500 Cartesian functions (l<=2), "
+                               "J + full-range K + long-range K, omega=0.3, tau=1e-10, FP64",
+                   "n_atoms": mol.n_atoms, "n_bf": mol.n_bf, "tau": 1e-10, "precision": "fp64"},
+        "wall_s": ms_step * 1e-3,
+        "quartets": quartets,
+        "prim_quartets": st["prim_quartets"],
+        "kernel_ms": float(class_ms.sum()),
+        "kernel_quartets_per_s": quartets / (class_ms.sum() * 1e-3),
+        "plan_s": plan_s,
+        "roofline": {"bound": "alu", "kernel": "k_deriv" + str(tdgrad.CLASSES[dom]),
+                     "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                     "all_classes_achieved": all_tflops,
+                     "all_classes_frac": all_tflops / FP64_VALU_PEAK_TFLOPS},
+        "class_ms": {str(c): round(float(m), 4) for c, m in zip(tdgrad.CLASSES, class_ms)},
+        "mixed": None,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(mol, args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

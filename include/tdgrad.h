@@ -1,0 +1,142 @@
+/*
+ * tdgrad.h -- C ABI of the MI355X (gfx950) library for the two-electron part
+ * of the TDA-TDDFT nuclear gradient with range-separated hybrid functionals.
+ *
+ * The library computes (paper section II.A, eq dE_ao, fourth and fifth terms)
+ *
+ *   G[A][x] = sum_{mu nu lam sig} Gamma_{mu nu lam sig}    d(mu nu|lam sig)   /dA_x
+ *                               + Gamma^lr_{mu nu lam sig} d(mu nu|lam sig)_lr/dA_x
+ *
+ * with the two-particle densities of eq gamma,
+ *   Gamma    = 2 R_{nu mu} R_{lam sig} - alpha R_{sig mu} R_{lam nu}
+ *              + 1/2 ( D_{mu nu} P_{lam sig} - alpha/2 D_{mu sig} P_{lam nu} )
+ *   Gamma^lr = - beta R_{sig mu} R_{lam nu} - beta/4 D_{mu sig} P_{lam nu},
+ * where P is the ground-state density P0, D = P0 + 2 PDelta, R the TDA
+ * transition density, (..|..) the Coulomb ERI of eq eri_j and (..|..)_lr the
+ * erf(omega r)/r ERI of eq lreri_k, over contracted Cartesian Gaussians of
+ * eq cartG with l <= 2.  The derivative of each quartet follows eqs deri,
+ * deriv, ti and eriupdate (section II.C); the integrals are evaluated by Rys
+ * quadrature in hand-written HIP kernels.  Units: hartree/bohr; the output is
+ * dE/dA (the gradient, not the force).
+ *
+ * Conventions
+ *   - Every Cartesian component is normalised to one (primitive, contraction
+ *     and angular factor).  Components of a shell are ordered lx descending,
+ *     then ly descending: p = x,y,z; d = xx,xy,xz,yy,yz,zz.
+ *   - Density matrices are FP64, row-major n_bf x n_bf, in the AO order given
+ *     by shell_ao_off.  P0 and PDelta must be symmetric (only their symmetric
+ *     part enters); R is general.
+ *   - All entry points return TDG_OK (0) or a negative tdg_status; they never
+ *     abort or throw.  tdg_last_error() returns a thread-local message.
+ *   - On error no partial result is written to grad.
+ *
+ * Ownership
+ *   - The caller owns every input and output buffer; the library never frees them.
+ *   - A plan owns its device tables and work buffers; free it with tdg_plan_destroy.
+ *   - ptr_kind = 1: densities and grad are device pointers on the plan's device;
+ *     the call is asynchronous on hip_stream (the caller synchronises).
+ *     ptr_kind = 0: host pointers; the call returns after the result is copied.
+ *   - Calls on one plan must not overlap (a plan holds one set of work buffers).
+ */
+#ifndef TDGRAD_H
+#define TDGRAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TDG_OK = 0,
+    TDG_EINVAL = -1,        /* null pointer, negative size, index out of range */
+    TDG_EUNSUPPORTED = -2,  /* l > 2, too many primitives, unsupported option */
+    TDG_ENOMEM = -3,        /* device or host allocation failed */
+    TDG_EDEVICE = -4,       /* a HIP runtime call failed */
+    TDG_ESTATE = -5         /* plan in an unusable state */
+} tdg_status;
+
+typedef struct tdg_plan tdg_plan_t; /* opaque */
+
+/* Basis and geometry (host pointers, copied by tdg_plan_create). */
+typedef struct {
+    int32_t n_atoms;
+    const double *coords;          /* [n_atoms][3], bohr */
+    int32_t n_shells;
+    const int32_t *shell_atom;     /* [n_shells] atom index */
+    const int32_t *shell_l;        /* [n_shells] angular momentum, 0..2 */
+    const int32_t *shell_nprim;    /* [n_shells] contraction degree, 1..TDG_MAX_NPRIM */
+    const int32_t *shell_prim_off; /* [n_shells] offset into exps/coefs */
+    const int32_t *shell_ao_off;   /* [n_shells] first AO index of the shell */
+    int32_t n_prims;
+    const double *exps;            /* [n_prims] Gaussian exponents zeta > 0 */
+    const double *coefs;           /* [n_prims] contraction coefficients of unnormalised primitives */
+} tdg_basis_t;
+
+#define TDG_MAX_NPRIM 16
+
+/* Method parameters (section II.A: alpha is the short-range HF fraction,
+ * alpha + beta the long-range one, omega the range-separation parameter;
+ * section II.E: density-multiplied Schwarz threshold). */
+typedef struct {
+    double omega;       /* bohr^-1, > 0 when terms has bit 4 */
+    double alpha;       /* full-range exchange fraction */
+    double beta;        /* long-range exchange fraction */
+    double schwarz_tol; /* skip a quartet when Q_ab Q_cd M_abcd < schwarz_tol; 0 = no screening */
+    int32_t precision;  /* 0: FP64 throughout (the only value accepted so far) */
+    int32_t terms;      /* bit 1: Coulomb-type (J) terms, bit 2: full-range exchange (alpha),
+                           bit 4: long-range exchange (beta); 7 = all */
+} tdg_params_t;
+
+/* Per-call statistics (optional output). */
+typedef struct {
+    int64_t quartets;          /* shell quartets evaluated after screening */
+    int64_t prim_quartets;     /* primitive quartets of those */
+    int64_t candidates;        /* shell quartets tested by the exact screening bound */
+    int64_t class_quartets[21];/* per angular class, in the library's class order */
+    int64_t class_prim_quartets[21];
+    double class_ms[21];       /* derivative-kernel time per class (HIP events on the call's stream) */
+    double ms_total;           /* wall time of the call (host clock, synchronised) */
+    double ms_kernels;         /* summed derivative-kernel time (HIP events) */
+} tdg_stats_t;
+
+/* Build a plan for one geometry and basis on HIP device `device`:
+ * normalisation, shell-pair tables, Schwarz factors Q_ab = sqrt(max (mu nu|mu nu)),
+ * pair lists sorted by class, contraction degree and Q.
+ * Errors: TDG_EINVAL (bad pointers/indices), TDG_EUNSUPPORTED (l > 2 or
+ * nprim > TDG_MAX_NPRIM), TDG_ENOMEM, TDG_EDEVICE. */
+int tdg_plan_create(const tdg_basis_t *basis, const tdg_params_t *params, int device,
+                    tdg_plan_t **out);
+
+/* Two-electron gradient for one set of densities (eq dE_ao terms 4-5).
+ * P0, PDelta, R: [n_bf][n_bf] FP64 row-major; grad: [n_atoms][3] FP64,
+ * overwritten.  ptr_kind 0: host pointers (synchronous); 1: device pointers,
+ * asynchronous on hip_stream (a hipStream_t, NULL = default stream).
+ * stats may be NULL; when given, the call synchronises the stream to fill it.
+ * Errors: TDG_EINVAL, TDG_ENOMEM, TDG_EDEVICE, TDG_ESTATE. */
+int tdg_grad_jk(tdg_plan_t *plan, const double *P0, const double *PDelta, const double *R,
+                int32_t ptr_kind, void *hip_stream, double *grad, tdg_stats_t *stats);
+
+/* Release a plan and its device memory (NULL is accepted). */
+int tdg_plan_destroy(tdg_plan_t *plan);
+
+/* Number of basis functions and atoms of a plan (for callers sizing buffers). */
+int tdg_plan_dims(const tdg_plan_t *plan, int32_t *n_bf, int32_t *n_atoms, int32_t *n_shells);
+
+/* Schwarz factor of every shell pair, copied to host: Q[a*(a+1)/2 + b] for a >= b
+ * (shell indices of the caller's basis).  Q must hold n_shells*(n_shells+1)/2 doubles. */
+int tdg_plan_schwarz(const tdg_plan_t *plan, double *Q);
+
+/* Rys quadrature rule used by the kernels (for verification): for n roots
+ * (1..5) and argument T >= 0, u[i] (= t_i^2, ascending) and w[i].  Evaluated
+ * on the device of the plan-less default device 0; u and w are host arrays of n. */
+int tdg_rys_rule(int32_t n, double T, double *u, double *w);
+
+/* Thread-local description of the last failure ("" if none). */
+const char *tdg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDGRAD_H */

@@ -406,7 +406,7 @@ static void deriv_blocks(const oshell_t *s[4], int op, double omega, double *der
         const oshell_t *su[4] = {s[0], s[1], s[2], s[3]}, *sd[4] = {s[0], s[1], s[2], s[3]};
         su[X] = &up;
         sd[X] = &dn;
-        eri_block(su[0], su[1], su[2], su[3], op, omega, bu, np);
+        eri_block(su[0], su[1], su[2], su[3], op, omega, bu, X == 0 ? np : NULL); /* count once */
         if (bd) eri_block(sd[0], sd[1], sd[2], sd[3], op, omega, bd, NULL);
         for (int c0 = 0; c0 < n[0]; ++c0)
             for (int c1 = 0; c1 < n[1]; ++c1)

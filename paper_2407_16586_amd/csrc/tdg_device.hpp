@@ -1,0 +1,111 @@
+// Device-side helpers shared by the tdgrad kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rys_table.inc"
+
+namespace tdg {
+
+constexpr int kWave = 64;
+
+__host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+// Cartesian exponents of component i of a shell with angular momentum l,
+// ordered lx descending then ly descending (x,y,z; xx,xy,xz,yy,yz,zz).
+struct Cart {
+    int v[3][6][3];
+};
+__host__ __device__ constexpr Cart make_cart()
+{
+    Cart c{};
+    for (int l = 0; l <= 2; ++l) {
+        int n = 0;
+        for (int lx = l; lx >= 0; --lx)
+            for (int ly = l - lx; ly >= 0; --ly) {
+                c.v[l][n][0] = lx;
+                c.v[l][n][1] = ly;
+                c.v[l][n][2] = l - lx - ly;
+                ++n;
+            }
+    }
+    return c;
+}
+constexpr Cart kCart = make_cart();
+
+// number of Rys roots for the derivative of a class of total angular momentum L:
+// the raised integral has momentum L+1, so floor((L+1)/2) + 1 roots
+__host__ __device__ constexpr int nroots_deriv(int L) { return (L + 1) / 2 + 1; }
+
+// Make LDS writes of one lane visible to the other lanes of its wavefront.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------------------ Rys rule
+template <int N> __device__ __forceinline__ const double *rys_poly();
+template <> __device__ __forceinline__ const double *rys_poly<1>() { return rys_poly_1; }
+template <> __device__ __forceinline__ const double *rys_poly<2>() { return rys_poly_2; }
+template <> __device__ __forceinline__ const double *rys_poly<3>() { return rys_poly_3; }
+template <> __device__ __forceinline__ const double *rys_poly<4>() { return rys_poly_4; }
+template <> __device__ __forceinline__ const double *rys_poly<5>() { return rys_poly_5; }
+template <int N> __device__ __forceinline__ const double *rys_hx();
+template <> __device__ __forceinline__ const double *rys_hx<1>() { return rys_herm_x_1; }
+template <> __device__ __forceinline__ const double *rys_hx<2>() { return rys_herm_x_2; }
+template <> __device__ __forceinline__ const double *rys_hx<3>() { return rys_herm_x_3; }
+template <> __device__ __forceinline__ const double *rys_hx<4>() { return rys_herm_x_4; }
+template <> __device__ __forceinline__ const double *rys_hx<5>() { return rys_herm_x_5; }
+template <int N> __device__ __forceinline__ const double *rys_hw();
+template <> __device__ __forceinline__ const double *rys_hw<1>() { return rys_herm_w_1; }
+template <> __device__ __forceinline__ const double *rys_hw<2>() { return rys_herm_w_2; }
+template <> __device__ __forceinline__ const double *rys_hw<3>() { return rys_herm_w_3; }
+template <> __device__ __forceinline__ const double *rys_hw<4>() { return rys_herm_w_4; }
+template <> __device__ __forceinline__ const double *rys_hw<5>() { return rys_herm_w_5; }
+
+// Root r (0-based, ascending) and weight of the N-point Rys rule at argument T >= 0:
+// sum_r w_r u_r^k = F_k(T) for k < 2N.
+template <int N>
+__device__ __forceinline__ void rys_root(double T, int r, double &u, double &w)
+{
+    if (T < RYS_TMAX) {
+        const int j = (int)(T * (1.0 / RYS_WIDTH));
+        const double x = T - RYS_WIDTH * (j + 0.5);
+        const double *cu = rys_poly<N>() + ((j * 2 * N) + r) * RYS_NCOEF;
+        const double *cw = cu + N * RYS_NCOEF;
+        double a = cu[RYS_NCOEF - 1], b = cw[RYS_NCOEF - 1];
+#pragma unroll
+        for (int k = RYS_NCOEF - 2; k >= 0; --k) {
+            a = fma(a, x, cu[k]);
+            b = fma(b, x, cw[k]);
+        }
+        u = a;
+        w = b;
+    } else {
+        const double it = 1.0 / T;
+        const double xh = rys_hx<N>()[r];
+        u = xh * xh * it;
+        w = rys_hw<N>()[r] * sqrt(it);
+    }
+}
+
+__device__ __forceinline__ void rys_root_rt(int n, double T, int r, double &u, double &w)
+{
+    switch (n) {
+    case 1: rys_root<1>(T, r, u, w); break;
+    case 2: rys_root<2>(T, r, u, w); break;
+    case 3: rys_root<3>(T, r, u, w); break;
+    case 4: rys_root<4>(T, r, u, w); break;
+    default: rys_root<5>(T, r, u, w); break;
+    }
+}
+
+// ---------------------------------------------------------------- atomics
+__device__ __forceinline__ void atomic_add_global(double *p, double v)
+{
+    unsafeAtomicAdd(p, v); // global_atomic_add_f64 (coarse-grained device memory)
+}
+
+} // namespace tdg

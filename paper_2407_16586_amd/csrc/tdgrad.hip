@@ -1,0 +1,878 @@
+// tdgrad.hip -- host runtime, set-up kernels and C ABI of libtdgrad.so.
+//
+// Pipeline of one gradient call (all on the caller's stream):
+//   a3 density preparation: angular normalisation folded into P0, D = P0 + 2 PDelta
+//      and R; shell-block maxima of |P0|, |D|, |R| for the screening bound;
+//   a4 task generation: for each of the 21 angular classes and each bra pair, the
+//      ket pairs whose density-multiplied Schwarz bound passes (section II.E),
+//      found as a Q-sorted prefix per contraction group, then tested exactly;
+//   a5-a10 one class kernel per class (deriv_kernel.hpp), accumulating into the
+//      per-atom FP64 gradient.
+// The plan (tdg_plan_create) holds a1-a2: normalisation, shell pairs, primitive
+// pairs and Schwarz factors, sorted by class, contraction degree and Q (D1 of
+// section II.C: presorted shell-pair lists).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/tdgrad.h"
+#include "deriv_kernel.hpp"
+
+using namespace tdg;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(TDG_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------- constants
+static constexpr int kPairL[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
+static int pair_class(int la, int lb) // la >= lb
+{
+    static const int tab[3][3] = {{0, -1, -1}, {1, 2, -1}, {3, 4, 5}};
+    return tab[la][lb];
+}
+static constexpr int kNumClasses = 21;
+// class index c <-> (bra pair class PB, ket pair class PK), PB >= PK
+static void class_pk(int c, int &pb, int &pk)
+{
+    int k = 0;
+    for (int b = 0; b < 6; ++b)
+        for (int q = 0; q <= b; ++q, ++k)
+            if (k == c) { pb = b; pk = q; return; }
+}
+
+template <class T> struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    int alloc(size_t count)
+    {
+        if (count <= n && p) return 0;
+        if (p) hipFree(p);
+        p = nullptr;
+        n = 0;
+        if (count == 0) return 0;
+        if (hipMalloc((void **)&p, count * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            return fail(TDG_ENOMEM, "hipMalloc of %zu bytes failed", count * sizeof(T));
+        }
+        n = count;
+        return 0;
+    }
+    int upload(const std::vector<T> &h)
+    {
+        int rc = alloc(h.size());
+        if (rc) return rc;
+        if (!h.empty() && hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(TDG_EDEVICE, "hipMemcpy upload failed");
+        return 0;
+    }
+    void release()
+    {
+        if (p) hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+struct tdg_plan {
+    int device = 0;
+    int n_atoms = 0, n_shells = 0, n_prims = 0, n_bf = 0;
+    tdg_params_t prm{};
+    std::vector<int> shell_atom, shell_l, shell_ao;
+    // sorted pairs
+    int npair = 0;
+    int pc_start[7] = {0};                 // pair-class segments of the sorted list
+    std::vector<int> grp_start;            // contraction groups (equal Ka*Kb) inside a class
+    std::vector<int> pc_grp_start;         // [7] index into grp_start per pair class
+    std::vector<int> pair_sa, pair_sb, pair_K;
+    std::vector<double> pair_Q;
+    std::vector<int> user_pair_to_sorted;  // by a*(a+1)/2+b with a>=b in caller's shell order
+    // device
+    DevBuf<double> d_coords;
+    DevBuf<int> d_shell_atom, d_shell_ao, d_shell_l;
+    DevBuf<int> d_pair_sa, d_pair_sb, d_pair_ppoff, d_pair_npp, d_pair_K;
+    DevBuf<double> d_pair_Q;
+    DevBuf<double> d_pp_p, d_pp_Px, d_pp_Py, d_pp_Pz, d_pp_c, d_pp_za, d_pp_zb;
+    DevBuf<double> d_ang;                  // angular normalisation per AO
+    DevBuf<int> d_grp_start;
+    // work buffers
+    DevBuf<double> d_in;                   // staging of host densities (3 n_bf^2)
+    DevBuf<double> d_Pn, d_Dn, d_Rn;
+    DevBuf<double> d_mP, d_mD, d_mR;       // [n_shells^2]
+    DevBuf<double> d_grad;
+    DevBuf<unsigned long long> d_mx;       // max of block maxima (bit pattern of a double >= 0)
+    DevBuf<int> d_item_cnt;                // per (class, bra pair) survivor counts
+    DevBuf<long long> d_item_off;
+    DevBuf<unsigned long long> d_prim_cnt; // per class primitive quartets
+    DevBuf<unsigned long long> d_cand_cnt; // per class candidates tested by the exact bound
+    DevBuf<int2> d_tasks;
+    std::vector<int> item_class_off;       // [22] offset of each class's items
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev_cls[kNumClasses + 1] = {};
+};
+
+// ======================================================================= a1
+static double dfact(int n)
+{
+    double r = 1.0;
+    for (int k = n; k > 1; k -= 2) r *= k;
+    return r;
+}
+
+// normalised contraction coefficients of the x^l component (unit self-overlap)
+static void normalise(int l, int np, const double *z, const double *d, double *c)
+{
+    for (int k = 0; k < np; ++k)
+        c[k] = d[k] * std::pow(2.0 * z[k] / M_PI, 0.75) * std::pow(4.0 * z[k], 0.5 * l) / std::sqrt(dfact(2 * l - 1));
+    double s = 0.0;
+    for (int i = 0; i < np; ++i)
+        for (int j = 0; j < np; ++j) {
+            const double zz = z[i] + z[j];
+            s += c[i] * c[j] * dfact(2 * l - 1) / std::pow(2.0 * zz, l) * std::pow(M_PI / zz, 1.5);
+        }
+    const double nc = 1.0 / std::sqrt(s);
+    for (int k = 0; k < np; ++k) c[k] *= nc;
+}
+
+static double ang_factor(int lx, int ly, int lz)
+{
+    const int l = lx + ly + lz;
+    return std::sqrt(dfact(2 * l - 1) / (dfact(2 * lx - 1) * dfact(2 * ly - 1) * dfact(2 * lz - 1)));
+}
+
+// ======================================================================= a2: Schwarz
+// Q_ab = sqrt(max over components (mu nu|mu nu)), (ab|ab) by Rys quadrature with
+// LA+LB+1 roots, one thread per pair.
+template <int LA, int LB>
+__global__ void k_schwarz(int npair, const int *pair_sa, const int *pair_sb, const int *ppoff, const int *npp,
+                          const int *shell_atom, const double *coords, const double *pp_p, const double *pp_Px,
+                          const double *pp_Py, const double *pp_Pz, const double *pp_c, const double *ang_ab,
+                          double *Q)
+{
+    constexpr int NR = LA + LB + 1, NA = ncart(LA), NB = ncart(LB);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npair) return;
+    const int sa = pair_sa[i], sb = pair_sb[i];
+    double A[3], AB[3];
+    for (int d = 0; d < 3; ++d) {
+        A[d] = coords[3 * shell_atom[sa] + d];
+        AB[d] = A[d] - coords[3 * shell_atom[sb] + d];
+    }
+    double acc[NA * NB];
+#pragma unroll
+    for (int k = 0; k < NA * NB; ++k) acc[k] = 0.0;
+    const int p0 = ppoff[i], n = npp[i];
+    for (int x = 0; x < n; ++x) {
+        const double p = pp_p[p0 + x], cx = pp_c[p0 + x];
+        const double P[3] = {pp_Px[p0 + x], pp_Py[p0 + x], pp_Pz[p0 + x]};
+        for (int y = 0; y < n; ++y) {
+            const double q = pp_p[p0 + y], cy = pp_c[p0 + y];
+            const double Qc[3] = {pp_Px[p0 + y], pp_Py[p0 + y], pp_Pz[p0 + y]};
+            const double ipq = 1.0 / (p + q), rho = p * q * ipq;
+            double PQ[3], pq2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                PQ[d] = P[d] - Qc[d];
+                pq2 += PQ[d] * PQ[d];
+            }
+            const double pref = 34.98683665524972 / (p * q) * sqrt(ipq) * cx * cy;
+            for (int r = 0; r < NR; ++r) {
+                double u, w;
+                rys_root<NR>(rho * pq2, r, u, w);
+                const double B00 = 0.5 * u * ipq, B10 = 0.5 / p * (1.0 - q * ipq * u), B01 = 0.5 / q * (1.0 - p * ipq * u);
+                Rys2D<LA + LB, LA + LB, LA, LB, LB> g[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double PA = P[d] - A[d], QC = Qc[d] - A[d];
+                    g[d].build(d == 2 ? pref * w : 1.0, PA - q * ipq * u * PQ[d], QC + p * ipq * u * PQ[d], B10, B01,
+                               B00, AB[d], AB[d]);
+                }
+#pragma unroll
+                for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                    for (int ib = 0; ib < NB; ++ib) {
+                        double v = 1.0;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const int ii = kCart.v[LA][ia][d], jj = kCart.v[LB][ib][d];
+                            v *= g[d].X[ii][jj][ii][jj];
+                        }
+                        acc[ia * NB + ib] += v;
+                    }
+            }
+        }
+    }
+    double mx = 0.0;
+#pragma unroll
+    for (int k = 0; k < NA * NB; ++k) mx = fmax(mx, acc[k] * ang_ab[k]);
+    Q[i] = sqrt(mx);
+}
+
+// ======================================================================= a3
+// scaled densities and shell-block maxima; one thread per shell block (a, c)
+__global__ void k_density_prep(int n_shells, int n_bf, const int *shell_l, const int *shell_ao, const double *ang,
+                               const double *P0, const double *PD, const double *R, double *Pn, double *Dn,
+                               double *Rn, double *mP, double *mD, double *mR, unsigned long long *mx)
+{
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)n_shells * n_shells) return;
+    const int a = (int)(idx / n_shells), c = (int)(idx % n_shells);
+    const int oa = shell_ao[a], oc = shell_ao[c], na = ncart(shell_l[a]), nc = ncart(shell_l[c]);
+    double vp = 0.0, vd = 0.0, vr = 0.0;
+    for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nc; ++j) {
+            const size_t ij = (size_t)(oa + i) * n_bf + (oc + j), ji = (size_t)(oc + j) * n_bf + (oa + i);
+            const double p = P0[ij], d = P0[ij] + 2.0 * PD[ij], rr = R[ij];
+            const double s = ang[oa + i] * ang[oc + j];
+            Pn[ij] = s * p;
+            Dn[ij] = s * d;
+            Rn[ij] = s * rr;
+            vp = fmax(vp, fabs(p));
+            vd = fmax(vd, fabs(d));
+            vr = fmax(vr, fmax(fabs(rr), fabs(R[ji])));
+        }
+    mP[idx] = vp;
+    mD[idx] = vd;
+    mR[idx] = vr;
+    const double m = fmax(vp, fmax(vd, vr));
+    atomicMax(mx, (unsigned long long)__double_as_longlong(m)); // non-negative doubles order as integers
+}
+
+// ======================================================================= a4
+struct ScreenArgs {
+    int cls, pb, pk;
+    int bra0, nbra;               // bra pairs of this class: sorted indices [bra0, bra0+nbra)
+    int grp0, grp1;               // contraction groups of the ket pair class
+    const int *grp_start;         // [ngroups+1]
+    const int *pair_sa, *pair_sb, *pair_K, *shell_atom;
+    const double *pair_Q;
+    const double *mP, *mD, *mR;
+    int n_shells;
+    double tau;
+    const unsigned long long *mx;
+    int *item_cnt;                // count pass output, per bra
+    const long long *item_off;    // fill pass input (absolute task index of each bra's first task)
+    int2 *tasks;
+    unsigned long long *prim_cnt; // per class
+    unsigned long long *cand_cnt; // per class
+};
+
+__device__ __forceinline__ double quartet_bound(const ScreenArgs &s, int a, int b, int c, int d, double Qab, double Qcd)
+{
+    const size_t n = s.n_shells;
+#define B_(X, i, j) s.X[(size_t)(i) * n + (j)]
+    double m = B_(mD, a, b) * B_(mP, c, d);
+    m = fmax(m, B_(mP, a, b) * B_(mD, c, d));
+    m = fmax(m, B_(mR, a, b) * B_(mR, c, d));
+    m = fmax(m, B_(mD, a, c) * B_(mP, b, d));
+    m = fmax(m, B_(mD, b, d) * B_(mP, a, c));
+    m = fmax(m, B_(mD, a, d) * B_(mP, b, c));
+    m = fmax(m, B_(mD, b, c) * B_(mP, a, d));
+    m = fmax(m, B_(mR, a, c) * B_(mR, b, d));
+    m = fmax(m, B_(mR, a, d) * B_(mR, b, c));
+#undef B_
+    return Qab * Qcd * m;
+}
+
+// one wavefront per bra pair; FILL = false counts, true writes the tasks in order
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_screen(const ScreenArgs s)
+{
+    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+    if (wid >= s.nbra) return;
+    const int i = s.bra0 + wid;
+    const int a = s.pair_sa[i], b = s.pair_sb[i];
+    const double Qi = s.pair_Q[i];
+    const double mxv = __longlong_as_double((long long)*s.mx);
+    const double cut = s.tau > 0.0 ? s.tau / (Qi * mxv * mxv) : -1.0;
+    const int ata = s.shell_atom[a], atb = s.shell_atom[b];
+    const int Ki = s.pair_K[i];
+    long long out = FILL ? s.item_off[wid] : 0;
+    int cnt = 0;
+    unsigned long long prim = 0, cand = 0;
+    for (int g = s.grp0; g < s.grp1; ++g) {
+        const int g0 = s.grp_start[g], g1 = s.grp_start[g + 1];
+        int hi = g1;
+        if (cut > 0.0) { // first ket in the group with Q < cut (Q sorted descending)
+            int lo = g0;
+            hi = g1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s.pair_Q[mid] >= cut) lo = mid + 1; else hi = mid;
+            }
+        }
+        if (s.pb == s.pk && hi > i + 1) hi = i + 1; // canonical: ket index <= bra index
+        if (hi > g0) cand += hi - g0;
+        for (int j0 = g0; j0 < hi; j0 += kWave) {
+            const int j = j0 + lane;
+            bool keep = false;
+            if (j < hi) {
+                const int c = s.pair_sa[j], d = s.pair_sb[j];
+                const bool one_center = (s.shell_atom[c] == ata) && (s.shell_atom[d] == ata) && (atb == ata);
+                keep = !one_center && (s.tau <= 0.0 || quartet_bound(s, a, b, c, d, Qi, s.pair_Q[j]) >= s.tau);
+                if (keep) prim += (unsigned long long)Ki * s.pair_K[j];
+            }
+            const unsigned long long mask = __ballot(keep);
+            if (FILL && keep) {
+                const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+                s.tasks[out + rank] = make_int2(i, j);
+            }
+            const int nk = __popcll(mask);
+            out += nk;
+            cnt += nk;
+        }
+    }
+    if (!FILL) {
+        // wave reduction of the primitive count
+        for (int off = 32; off > 0; off >>= 1) prim += __shfl_xor(prim, off);
+        if (lane == 0) {
+            s.item_cnt[wid] = cnt;
+            atomicAdd(s.prim_cnt + s.cls, prim);
+            atomicAdd(s.cand_cnt + s.cls, cand);
+        }
+    }
+}
+
+__global__ void k_zero(double *p, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// ======================================================================= dispatch
+template <int LA, int LB, int LC, int LD, bool LR>
+static hipError_t launch_one(const DerivArgs &a, hipStream_t st, int grid_max)
+{
+    using K = DerivClass<LA, LB, LC, LD, LR>;
+    const long long blocks_needed = (a.ntasks + K::TPB - 1) / K::TPB;
+    const int grid = (int)std::min<long long>(blocks_needed, grid_max);
+    const size_t dyn = a.lds_atoms ? (size_t)3 * a.n_atoms * sizeof(double) : 0;
+    hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+    return hipGetLastError();
+}
+
+template <int LA, int LB, int LC, int LD>
+static hipError_t launch_lr(const DerivArgs &a, bool lr, hipStream_t st, int grid_max)
+{
+    return lr ? launch_one<LA, LB, LC, LD, true>(a, st, grid_max) : launch_one<LA, LB, LC, LD, false>(a, st, grid_max);
+}
+
+static hipError_t launch_class(int c, const DerivArgs &a, bool lr, hipStream_t st, int grid_max)
+{
+    switch (c) {
+    case 0: return launch_lr<0, 0, 0, 0>(a, lr, st, grid_max);
+    case 1: return launch_lr<1, 0, 0, 0>(a, lr, st, grid_max);
+    case 2: return launch_lr<1, 0, 1, 0>(a, lr, st, grid_max);
+    case 3: return launch_lr<1, 1, 0, 0>(a, lr, st, grid_max);
+    case 4: return launch_lr<1, 1, 1, 0>(a, lr, st, grid_max);
+    case 5: return launch_lr<1, 1, 1, 1>(a, lr, st, grid_max);
+    case 6: return launch_lr<2, 0, 0, 0>(a, lr, st, grid_max);
+    case 7: return launch_lr<2, 0, 1, 0>(a, lr, st, grid_max);
+    case 8: return launch_lr<2, 0, 1, 1>(a, lr, st, grid_max);
+    case 9: return launch_lr<2, 0, 2, 0>(a, lr, st, grid_max);
+    case 10: return launch_lr<2, 1, 0, 0>(a, lr, st, grid_max);
+    case 11: return launch_lr<2, 1, 1, 0>(a, lr, st, grid_max);
+    case 12: return launch_lr<2, 1, 1, 1>(a, lr, st, grid_max);
+    case 13: return launch_lr<2, 1, 2, 0>(a, lr, st, grid_max);
+    case 14: return launch_lr<2, 1, 2, 1>(a, lr, st, grid_max);
+    case 15: return launch_lr<2, 2, 0, 0>(a, lr, st, grid_max);
+    case 16: return launch_lr<2, 2, 1, 0>(a, lr, st, grid_max);
+    case 17: return launch_lr<2, 2, 1, 1>(a, lr, st, grid_max);
+    case 18: return launch_lr<2, 2, 2, 0>(a, lr, st, grid_max);
+    case 19: return launch_lr<2, 2, 2, 1>(a, lr, st, grid_max);
+    default: return launch_lr<2, 2, 2, 2>(a, lr, st, grid_max);
+    }
+}
+
+template <int LA, int LB>
+static void launch_schwarz(tdg_plan *pl, int i0, int n, const double *ang_ab, double *Q)
+{
+    const int bs = 64;
+    hipLaunchKernelGGL((k_schwarz<LA, LB>), dim3((n + bs - 1) / bs), dim3(bs), 0, 0, n, pl->d_pair_sa.p + i0,
+                       pl->d_pair_sb.p + i0, pl->d_pair_ppoff.p + i0, pl->d_pair_npp.p + i0, pl->d_shell_atom.p,
+                       pl->d_coords.p, pl->d_pp_p.p, pl->d_pp_Px.p, pl->d_pp_Py.p, pl->d_pp_Pz.p, pl->d_pp_c.p,
+                       ang_ab, Q + i0);
+}
+
+// ======================================================================= plan
+static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
+{
+    const int ns = b->n_shells;
+    pl->n_atoms = b->n_atoms;
+    pl->n_shells = ns;
+    pl->n_prims = b->n_prims;
+    pl->shell_atom.assign(b->shell_atom, b->shell_atom + ns);
+    pl->shell_l.assign(b->shell_l, b->shell_l + ns);
+    pl->shell_ao.assign(b->shell_ao_off, b->shell_ao_off + ns);
+    int nbf = 0;
+    for (int s = 0; s < ns; ++s) nbf = std::max(nbf, b->shell_ao_off[s] + ncart(b->shell_l[s]));
+    pl->n_bf = nbf;
+
+    // a1: normalised coefficients and per-AO angular factors
+    std::vector<double> coef(b->n_prims);
+    for (int s = 0; s < ns; ++s)
+        normalise(b->shell_l[s], b->shell_nprim[s], b->exps + b->shell_prim_off[s], b->coefs + b->shell_prim_off[s],
+                  coef.data() + b->shell_prim_off[s]);
+    std::vector<double> ang(nbf, 1.0);
+    for (int s = 0; s < ns; ++s)
+        for (int k = 0; k < ncart(b->shell_l[s]); ++k) {
+            const int *t = kCart.v[b->shell_l[s]][k];
+            ang[b->shell_ao_off[s] + k] = ang_factor(t[0], t[1], t[2]);
+        }
+
+    // a2: canonical pairs (first shell has the higher l; equal l: higher index first)
+    struct PairRec { int sa, sb, cls, K; long long user; };
+    std::vector<PairRec> pr;
+    pr.reserve((size_t)ns * (ns + 1) / 2);
+    for (int x = 0; x < ns; ++x)
+        for (int y = 0; y <= x; ++y) {
+            int sa = x, sb = y;
+            if (b->shell_l[sb] > b->shell_l[sa]) std::swap(sa, sb);
+            pr.push_back({sa, sb, pair_class(b->shell_l[sa], b->shell_l[sb]), b->shell_nprim[sa] * b->shell_nprim[sb],
+                          (long long)x * (x + 1) / 2 + y});
+        }
+    const int np = (int)pr.size();
+    // primitive pairs in the unsorted order first (for the Schwarz pass)
+    auto build_pp = [&](const std::vector<PairRec> &v, std::vector<int> &off, std::vector<int> &cnt,
+                        std::vector<double> *pp) {
+        off.resize(v.size());
+        cnt.resize(v.size());
+        for (int k = 0; k < 7; ++k) pp[k].clear();
+        for (size_t i = 0; i < v.size(); ++i) {
+            const int sa = v[i].sa, sb = v[i].sb;
+            const double *A = b->coords + 3 * b->shell_atom[sa], *B = b->coords + 3 * b->shell_atom[sb];
+            const double ab2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
+            off[i] = (int)pp[0].size();
+            for (int ka = 0; ka < b->shell_nprim[sa]; ++ka)
+                for (int kb = 0; kb < b->shell_nprim[sb]; ++kb) {
+                    const double za = b->exps[b->shell_prim_off[sa] + ka], zb = b->exps[b->shell_prim_off[sb] + kb];
+                    const double p = za + zb;
+                    const double c = coef[b->shell_prim_off[sa] + ka] * coef[b->shell_prim_off[sb] + kb] *
+                                     std::exp(-za * zb / p * ab2);
+                    pp[0].push_back(p);
+                    for (int d = 0; d < 3; ++d) pp[1 + d].push_back((za * A[d] + zb * B[d]) / p);
+                    pp[4].push_back(c);
+                    pp[5].push_back(za);
+                    pp[6].push_back(zb);
+                }
+            cnt[i] = (int)pp[0].size() - off[i];
+        }
+    };
+    std::vector<int> off, cnt;
+    std::vector<double> pp[7];
+    build_pp(pr, off, cnt, pp);
+    if (pp[0].size() > (size_t)0x7fffffff) return fail(TDG_EUNSUPPORTED, "too many primitive pairs");
+
+    int rc;
+    std::vector<int> sa(np), sb(np);
+    for (int i = 0; i < np; ++i) { sa[i] = pr[i].sa; sb[i] = pr[i].sb; }
+    std::vector<double> coords(b->coords, b->coords + 3 * b->n_atoms);
+    if ((rc = pl->d_coords.upload(coords)) || (rc = pl->d_shell_atom.upload(pl->shell_atom)) ||
+        (rc = pl->d_shell_ao.upload(pl->shell_ao)) || (rc = pl->d_shell_l.upload(pl->shell_l)) ||
+        (rc = pl->d_pair_sa.upload(sa)) || (rc = pl->d_pair_sb.upload(sb)) || (rc = pl->d_pair_ppoff.upload(off)) ||
+        (rc = pl->d_pair_npp.upload(cnt)) || (rc = pl->d_pp_p.upload(pp[0])) || (rc = pl->d_pp_Px.upload(pp[1])) ||
+        (rc = pl->d_pp_Py.upload(pp[2])) || (rc = pl->d_pp_Pz.upload(pp[3])) || (rc = pl->d_pp_c.upload(pp[4])) ||
+        (rc = pl->d_pp_za.upload(pp[5])) || (rc = pl->d_pp_zb.upload(pp[6])) || (rc = pl->d_ang.upload(ang)))
+        return rc;
+
+    // Schwarz per pair class: pairs grouped by class for the templated kernel
+    std::vector<int> order(np);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pr[x].cls < pr[y].cls; });
+    {
+        std::vector<PairRec> pr2(np);
+        for (int i = 0; i < np; ++i) pr2[i] = pr[order[i]];
+        pr.swap(pr2);
+        for (int i = 0; i < np; ++i) { sa[i] = pr[i].sa; sb[i] = pr[i].sb; }
+        build_pp(pr, off, cnt, pp);
+        if ((rc = pl->d_pair_sa.upload(sa)) || (rc = pl->d_pair_sb.upload(sb)) || (rc = pl->d_pair_ppoff.upload(off)) ||
+            (rc = pl->d_pair_npp.upload(cnt)) || (rc = pl->d_pp_p.upload(pp[0])) || (rc = pl->d_pp_Px.upload(pp[1])) ||
+            (rc = pl->d_pp_Py.upload(pp[2])) || (rc = pl->d_pp_Pz.upload(pp[3])) || (rc = pl->d_pp_c.upload(pp[4])) ||
+            (rc = pl->d_pp_za.upload(pp[5])) || (rc = pl->d_pp_zb.upload(pp[6])))
+            return rc;
+    }
+    int cs[7] = {0};
+    for (int i = 0; i < np; ++i) cs[pr[i].cls + 1]++;
+    for (int k = 0; k < 6; ++k) cs[k + 1] += cs[k];
+    // angular factors of (mu nu|mu nu): (n_mu n_nu)^2 per pair class
+    std::vector<double> angab(6 * 36, 1.0);
+    for (int c = 0; c < 6; ++c) {
+        const int la = kPairL[c][0], lb = kPairL[c][1];
+        for (int ia = 0; ia < ncart(la); ++ia)
+            for (int ib = 0; ib < ncart(lb); ++ib) {
+                const int *ta = kCart.v[la][ia], *tb = kCart.v[lb][ib];
+                const double f = ang_factor(ta[0], ta[1], ta[2]) * ang_factor(tb[0], tb[1], tb[2]);
+                angab[c * 36 + ia * ncart(lb) + ib] = f * f;
+            }
+    }
+    DevBuf<double> d_angab, d_Q;
+    if ((rc = d_angab.upload(angab)) || (rc = d_Q.alloc(np))) return rc;
+    for (int c = 0; c < 6; ++c) {
+        const int n = cs[c + 1] - cs[c];
+        if (!n) continue;
+        const double *ang_c = d_angab.p + c * 36;
+        switch (c) {
+        case 0: launch_schwarz<0, 0>(pl, cs[c], n, ang_c, d_Q.p); break;
+        case 1: launch_schwarz<1, 0>(pl, cs[c], n, ang_c, d_Q.p); break;
+        case 2: launch_schwarz<1, 1>(pl, cs[c], n, ang_c, d_Q.p); break;
+        case 3: launch_schwarz<2, 0>(pl, cs[c], n, ang_c, d_Q.p); break;
+        case 4: launch_schwarz<2, 1>(pl, cs[c], n, ang_c, d_Q.p); break;
+        default: launch_schwarz<2, 2>(pl, cs[c], n, ang_c, d_Q.p); break;
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    std::vector<double> Q(np);
+    HIP_TRY(hipMemcpy(Q.data(), d_Q.p, sizeof(double) * np, hipMemcpyDeviceToHost));
+    d_Q.release();
+    d_angab.release();
+
+    // final order: class, contraction degree (descending), Q (descending)
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (pr[x].cls != pr[y].cls) return pr[x].cls < pr[y].cls;
+        if (pr[x].K != pr[y].K) return pr[x].K > pr[y].K;
+        return Q[x] > Q[y];
+    });
+    std::vector<PairRec> ps(np);
+    pl->pair_Q.resize(np);
+    pl->pair_K.resize(np);
+    pl->user_pair_to_sorted.assign(np, -1);
+    for (int i = 0; i < np; ++i) {
+        ps[i] = pr[order[i]];
+        pl->pair_Q[i] = Q[order[i]];
+        pl->pair_K[i] = ps[i].K;
+        pl->user_pair_to_sorted[ps[i].user] = i;
+    }
+    pl->npair = np;
+    pl->pair_sa.resize(np);
+    pl->pair_sb.resize(np);
+    for (int i = 0; i < np; ++i) { pl->pair_sa[i] = ps[i].sa; pl->pair_sb[i] = ps[i].sb; }
+    for (int k = 0; k < 7; ++k) pl->pc_start[k] = cs[k];
+    pl->grp_start.clear();
+    pl->pc_grp_start.assign(7, 0);
+    for (int c = 0; c < 6; ++c) {
+        pl->pc_grp_start[c] = (int)pl->grp_start.size();
+        for (int i = cs[c]; i < cs[c + 1]; ++i)
+            if (i == cs[c] || ps[i].K != ps[i - 1].K) pl->grp_start.push_back(i);
+    }
+    pl->pc_grp_start[6] = (int)pl->grp_start.size();
+    pl->grp_start.push_back(np);
+    build_pp(ps, off, cnt, pp);
+    if ((rc = pl->d_pair_sa.upload(pl->pair_sa)) || (rc = pl->d_pair_sb.upload(pl->pair_sb)) ||
+        (rc = pl->d_pair_ppoff.upload(off)) || (rc = pl->d_pair_npp.upload(cnt)) || (rc = pl->d_pair_K.upload(pl->pair_K)) ||
+        (rc = pl->d_pair_Q.upload(pl->pair_Q)) || (rc = pl->d_grp_start.upload(pl->grp_start)) ||
+        (rc = pl->d_pp_p.upload(pp[0])) || (rc = pl->d_pp_Px.upload(pp[1])) || (rc = pl->d_pp_Py.upload(pp[2])) ||
+        (rc = pl->d_pp_Pz.upload(pp[3])) || (rc = pl->d_pp_c.upload(pp[4])) || (rc = pl->d_pp_za.upload(pp[5])) ||
+        (rc = pl->d_pp_zb.upload(pp[6])))
+        return rc;
+    // screening items: (class, bra pair)
+    pl->item_class_off.assign(kNumClasses + 1, 0);
+    for (int c = 0; c < kNumClasses; ++c) {
+        int pb, pk;
+        class_pk(c, pb, pk);
+        pl->item_class_off[c + 1] = pl->item_class_off[c] + (cs[pb + 1] - cs[pb]);
+    }
+    const int nitems = pl->item_class_off[kNumClasses];
+    if ((rc = pl->d_item_cnt.alloc(std::max(nitems, 1))) || (rc = pl->d_item_off.alloc(std::max(nitems, 1))) ||
+        (rc = pl->d_prim_cnt.alloc(kNumClasses)) || (rc = pl->d_cand_cnt.alloc(kNumClasses)) || (rc = pl->d_mx.alloc(1)) ||
+        (rc = pl->d_grad.alloc((size_t)3 * pl->n_atoms)) || (rc = pl->d_Pn.alloc((size_t)nbf * nbf)) ||
+        (rc = pl->d_Dn.alloc((size_t)nbf * nbf)) || (rc = pl->d_Rn.alloc((size_t)nbf * nbf)) ||
+        (rc = pl->d_mP.alloc((size_t)ns * ns)) || (rc = pl->d_mD.alloc((size_t)ns * ns)) ||
+        (rc = pl->d_mR.alloc((size_t)ns * ns)))
+        return rc;
+    HIP_TRY(hipEventCreate(&pl->ev0));
+    HIP_TRY(hipEventCreate(&pl->ev1));
+    for (auto &e : pl->ev_cls) HIP_TRY(hipEventCreate(&e));
+    HIP_TRY(hipDeviceSynchronize());
+    return TDG_OK;
+}
+
+static int check_basis(const tdg_basis_t *b)
+{
+    if (!b || !b->coords || !b->shell_atom || !b->shell_l || !b->shell_nprim || !b->shell_prim_off ||
+        !b->shell_ao_off || !b->exps || !b->coefs)
+        return fail(TDG_EINVAL, "null pointer in basis");
+    if (b->n_atoms <= 0 || b->n_shells <= 0 || b->n_prims <= 0) return fail(TDG_EINVAL, "empty basis");
+    for (int s = 0; s < b->n_shells; ++s) {
+        if (b->shell_l[s] < 0 || b->shell_l[s] > 2) return fail(TDG_EUNSUPPORTED, "shell %d has l=%d (max 2)", s, b->shell_l[s]);
+        if (b->shell_nprim[s] < 1 || b->shell_nprim[s] > TDG_MAX_NPRIM)
+            return fail(TDG_EUNSUPPORTED, "shell %d has %d primitives (1..%d)", s, b->shell_nprim[s], TDG_MAX_NPRIM);
+        if (b->shell_atom[s] < 0 || b->shell_atom[s] >= b->n_atoms) return fail(TDG_EINVAL, "shell %d atom index out of range", s);
+        if (b->shell_prim_off[s] < 0 || b->shell_prim_off[s] + b->shell_nprim[s] > b->n_prims)
+            return fail(TDG_EINVAL, "shell %d primitive range out of bounds", s);
+        if (b->shell_ao_off[s] < 0) return fail(TDG_EINVAL, "shell %d negative AO offset", s);
+        for (int k = 0; k < b->shell_nprim[s]; ++k)
+            if (!(b->exps[b->shell_prim_off[s] + k] > 0.0)) return fail(TDG_EINVAL, "shell %d non-positive exponent", s);
+    }
+    return TDG_OK;
+}
+
+// ======================================================================= C ABI
+extern "C" {
+
+const char *tdg_last_error(void) { return g_err.c_str(); }
+
+int tdg_plan_create(const tdg_basis_t *basis, const tdg_params_t *params, int device, tdg_plan_t **out)
+{
+    g_err.clear();
+    if (!out || !params) return fail(TDG_EINVAL, "null argument");
+    *out = nullptr;
+    int rc = check_basis(basis);
+    if (rc) return rc;
+    if (params->precision != 0) return fail(TDG_EUNSUPPORTED, "precision mode %d not available", params->precision);
+    if ((params->terms & 4) && !(params->omega > 0.0)) return fail(TDG_EINVAL, "long-range term needs omega > 0");
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(TDG_EINVAL, "device %d not present (%d devices)", device, ndev);
+    HIP_TRY(hipSetDevice(device));
+    tdg_plan *pl = new (std::nothrow) tdg_plan();
+    if (!pl) return fail(TDG_ENOMEM, "host allocation failed");
+    pl->device = device;
+    pl->prm = *params;
+    rc = build_plan(pl, basis);
+    if (rc) {
+        tdg_plan_destroy(pl);
+        return rc;
+    }
+    *out = pl;
+    return TDG_OK;
+}
+
+int tdg_plan_destroy(tdg_plan_t *pl)
+{
+    if (!pl) return TDG_OK;
+    hipSetDevice(pl->device);
+    DevBuf<double> *dbl[] = {&pl->d_coords, &pl->d_pair_Q, &pl->d_pp_p, &pl->d_pp_Px, &pl->d_pp_Py, &pl->d_pp_Pz,
+                             &pl->d_pp_c, &pl->d_pp_za, &pl->d_pp_zb, &pl->d_ang, &pl->d_in, &pl->d_Pn, &pl->d_Dn,
+                             &pl->d_Rn, &pl->d_mP, &pl->d_mD, &pl->d_mR, &pl->d_grad};
+    for (auto *x : dbl) x->release();
+    DevBuf<int> *ints[] = {&pl->d_shell_atom, &pl->d_shell_ao, &pl->d_shell_l, &pl->d_pair_sa, &pl->d_pair_sb,
+                           &pl->d_pair_ppoff, &pl->d_pair_npp, &pl->d_pair_K, &pl->d_grp_start, &pl->d_item_cnt};
+    for (auto *x : ints) x->release();
+    pl->d_item_off.release();
+    pl->d_prim_cnt.release();
+    pl->d_cand_cnt.release();
+    for (auto &e : pl->ev_cls)
+        if (e) hipEventDestroy(e);
+    pl->d_mx.release();
+    pl->d_tasks.release();
+    if (pl->ev0) hipEventDestroy(pl->ev0);
+    if (pl->ev1) hipEventDestroy(pl->ev1);
+    delete pl;
+    return TDG_OK;
+}
+
+int tdg_plan_dims(const tdg_plan_t *pl, int32_t *n_bf, int32_t *n_atoms, int32_t *n_shells)
+{
+    if (!pl) return fail(TDG_EINVAL, "null plan");
+    if (n_bf) *n_bf = pl->n_bf;
+    if (n_atoms) *n_atoms = pl->n_atoms;
+    if (n_shells) *n_shells = pl->n_shells;
+    return TDG_OK;
+}
+
+int tdg_plan_schwarz(const tdg_plan_t *pl, double *Q)
+{
+    if (!pl || !Q) return fail(TDG_EINVAL, "null argument");
+    const long long ns = pl->n_shells;
+    for (long long k = 0; k < ns * (ns + 1) / 2; ++k) Q[k] = pl->pair_Q[pl->user_pair_to_sorted[k]];
+    return TDG_OK;
+}
+
+int tdg_grad_jk(tdg_plan_t *pl, const double *P0, const double *PD, const double *R, int32_t ptr_kind,
+                void *hip_stream, double *grad, tdg_stats_t *stats)
+{
+    g_err.clear();
+    if (!pl) return fail(TDG_EINVAL, "null plan");
+    if (!P0 || !PD || !R || !grad) return fail(TDG_EINVAL, "null density or output pointer");
+    if (ptr_kind != 0 && ptr_kind != 1) return fail(TDG_EINVAL, "ptr_kind must be 0 or 1");
+    const auto t_start = std::chrono::steady_clock::now();
+    HIP_TRY(hipSetDevice(pl->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int nbf = pl->n_bf, ns = pl->n_shells;
+    const size_t nn = (size_t)nbf * nbf;
+    int rc;
+    const double *dP0 = P0, *dPD = PD, *dR = R;
+    if (ptr_kind == 0) {
+        if ((rc = pl->d_in.alloc(3 * nn))) return rc;
+        HIP_TRY(hipMemcpyAsync(pl->d_in.p, P0, nn * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(pl->d_in.p + nn, PD, nn * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(pl->d_in.p + 2 * nn, R, nn * 8, hipMemcpyHostToDevice, st));
+        dP0 = pl->d_in.p;
+        dPD = pl->d_in.p + nn;
+        dR = pl->d_in.p + 2 * nn;
+    }
+    // a3
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (double *)pl->d_mx.p, 1);
+    hipLaunchKernelGGL(k_zero, dim3((3 * pl->n_atoms + 255) / 256), dim3(256), 0, st, pl->d_grad.p,
+                       (long long)3 * pl->n_atoms);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (double *)pl->d_prim_cnt.p, (long long)kNumClasses);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (double *)pl->d_cand_cnt.p, (long long)kNumClasses);
+    {
+        const long long nblk = (long long)ns * ns;
+        hipLaunchKernelGGL(k_density_prep, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, ns, nbf,
+                           pl->d_shell_l.p, pl->d_shell_ao.p, pl->d_ang.p, dP0, dPD, dR, pl->d_Pn.p, pl->d_Dn.p,
+                           pl->d_Rn.p, pl->d_mP.p, pl->d_mD.p, pl->d_mR.p, pl->d_mx.p);
+    }
+    HIP_TRY(hipGetLastError());
+    // a4: count
+    const double tau = pl->prm.schwarz_tol;
+    ScreenArgs s{};
+    s.grp_start = pl->d_grp_start.p;
+    s.pair_sa = pl->d_pair_sa.p; s.pair_sb = pl->d_pair_sb.p; s.pair_K = pl->d_pair_K.p;
+    s.shell_atom = pl->d_shell_atom.p; s.pair_Q = pl->d_pair_Q.p;
+    s.mP = pl->d_mP.p; s.mD = pl->d_mD.p; s.mR = pl->d_mR.p;
+    s.n_shells = ns; s.tau = tau; s.mx = pl->d_mx.p;
+    s.item_cnt = pl->d_item_cnt.p; s.item_off = pl->d_item_off.p; s.prim_cnt = pl->d_prim_cnt.p;
+    s.cand_cnt = pl->d_cand_cnt.p;
+    auto setup_class = [&](int c) {
+        int pb, pk;
+        class_pk(c, pb, pk);
+        s.cls = c; s.pb = pb; s.pk = pk;
+        s.bra0 = pl->pc_start[pb]; s.nbra = pl->pc_start[pb + 1] - pl->pc_start[pb];
+        s.grp0 = pl->pc_grp_start[pk]; s.grp1 = pl->pc_grp_start[pk + 1];
+        s.item_cnt = pl->d_item_cnt.p + pl->item_class_off[c];
+        s.item_off = pl->d_item_off.p + pl->item_class_off[c];
+    };
+    for (int c = 0; c < kNumClasses; ++c) {
+        setup_class(c);
+        if (s.nbra == 0 || s.grp1 == s.grp0) continue;
+        hipLaunchKernelGGL(k_screen<false>, dim3((s.nbra + 3) / 4), dim3(256), 0, st, s);
+    }
+    HIP_TRY(hipGetLastError());
+    const int nitems = pl->item_class_off[kNumClasses];
+    std::vector<int> cnt(nitems);
+    std::vector<unsigned long long> primc(kNumClasses), candc(kNumClasses);
+    if (nitems) HIP_TRY(hipMemcpyAsync(cnt.data(), pl->d_item_cnt.p, sizeof(int) * nitems, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(primc.data(), pl->d_prim_cnt.p, sizeof(unsigned long long) * kNumClasses,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(candc.data(), pl->d_cand_cnt.p, sizeof(unsigned long long) * kNumClasses,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    // empty classes were not launched: their counts are zero by construction
+    std::vector<long long> offs(nitems);
+    long long total = 0;
+    long long class_begin[kNumClasses + 1];
+    for (int c = 0; c < kNumClasses; ++c) {
+        setup_class(c);
+        class_begin[c] = total;
+        const bool launched = !(s.nbra == 0 || s.grp1 == s.grp0);
+        for (int k = pl->item_class_off[c]; k < pl->item_class_off[c + 1]; ++k) {
+            offs[k] = total;
+            if (launched) total += cnt[k];
+        }
+    }
+    class_begin[kNumClasses] = total;
+    if ((rc = pl->d_tasks.alloc(std::max<long long>(total, 1)))) return rc;
+    if (nitems) HIP_TRY(hipMemcpyAsync(pl->d_item_off.p, offs.data(), sizeof(long long) * nitems, hipMemcpyHostToDevice, st));
+    s.tasks = pl->d_tasks.p;
+    for (int c = 0; c < kNumClasses; ++c) {
+        setup_class(c);
+        if (s.nbra == 0 || s.grp1 == s.grp0 || class_begin[c + 1] == class_begin[c]) continue;
+        hipLaunchKernelGGL(k_screen<true>, dim3((s.nbra + 3) / 4), dim3(256), 0, st, s);
+    }
+    HIP_TRY(hipGetLastError());
+    // a5-a10
+    const bool lr = (pl->prm.terms & 4) && pl->prm.beta != 0.0;
+    DerivArgs a{};
+    a.coords = pl->d_coords.p; a.shell_atom = pl->d_shell_atom.p; a.shell_ao = pl->d_shell_ao.p;
+    a.pair_sa = pl->d_pair_sa.p; a.pair_sb = pl->d_pair_sb.p; a.pair_ppoff = pl->d_pair_ppoff.p;
+    a.pair_npp = pl->d_pair_npp.p;
+    a.pp_p = pl->d_pp_p.p; a.pp_Px = pl->d_pp_Px.p; a.pp_Py = pl->d_pp_Py.p; a.pp_Pz = pl->d_pp_Pz.p;
+    a.pp_c = pl->d_pp_c.p; a.pp_za = pl->d_pp_za.p; a.pp_zb = pl->d_pp_zb.p;
+    a.Pn = pl->d_Pn.p; a.Dn = pl->d_Dn.p; a.Rn = pl->d_Rn.p; a.n_bf = nbf;
+    a.omega = pl->prm.omega; a.alpha = pl->prm.alpha; a.beta = pl->prm.beta; a.terms = pl->prm.terms;
+    a.grad = pl->d_grad.p; a.n_atoms = pl->n_atoms;
+    a.lds_atoms = (3 * pl->n_atoms * 8 <= 24 * 1024) ? 1 : 0;
+    a.task_out = nullptr;
+    int ncu = 256;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, pl->device) == hipSuccess) ncu = prop.multiProcessorCount;
+    }
+    const int grid_max = ncu * 8;
+    HIP_TRY(hipEventRecord(pl->ev0, st));
+    for (int c = 0; c < kNumClasses; ++c) {
+        HIP_TRY(hipEventRecord(pl->ev_cls[c], st));
+        const long long n = class_begin[c + 1] - class_begin[c];
+        if (!n) continue;
+        a.tasks = pl->d_tasks.p + class_begin[c];
+        a.ntasks = n;
+        HIP_TRY(launch_class(c, a, lr, st, grid_max));
+    }
+    HIP_TRY(hipEventRecord(pl->ev_cls[kNumClasses], st));
+    HIP_TRY(hipEventRecord(pl->ev1, st));
+    if (ptr_kind == 0) {
+        HIP_TRY(hipMemcpyAsync(grad, pl->d_grad.p, sizeof(double) * 3 * pl->n_atoms, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    } else {
+        HIP_TRY(hipMemcpyAsync(grad, pl->d_grad.p, sizeof(double) * 3 * pl->n_atoms, hipMemcpyDeviceToDevice, st));
+    }
+    if (stats) {
+        HIP_TRY(hipStreamSynchronize(st));
+        std::memset(stats, 0, sizeof *stats);
+        for (int c = 0; c < kNumClasses; ++c) {
+            stats->class_quartets[c] = class_begin[c + 1] - class_begin[c];
+            stats->class_prim_quartets[c] = (long long)primc[c];
+            stats->prim_quartets += (long long)primc[c];
+            stats->candidates += (long long)candc[c];
+            float cm = 0.f;
+            HIP_TRY(hipEventElapsedTime(&cm, pl->ev_cls[c], pl->ev_cls[c + 1]));
+            stats->class_ms[c] = cm;
+        }
+        stats->quartets = total;
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
+        stats->ms_kernels = ms;
+        stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return TDG_OK;
+}
+
+} // extern "C"
+
+// device-side Rys rule for verification
+__global__ void k_rys_rule(int n, double T, double *u, double *w)
+{
+    const int r = threadIdx.x;
+    if (r < n) rys_root_rt(n, T, r, u[r], w[r]);
+}
+
+extern "C" int tdg_rys_rule(int32_t n, double T, double *u, double *w)
+{
+    g_err.clear();
+    if (n < 1 || n > 5 || !u || !w || !(T >= 0.0)) return fail(TDG_EINVAL, "bad arguments");
+    double *d = nullptr;
+    HIP_TRY(hipMalloc((void **)&d, 2 * 8 * sizeof(double)));
+    hipLaunchKernelGGL(k_rys_rule, dim3(1), dim3(64), 0, 0, n, T, d, d + 8);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(u, d, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(w, d + 8, n * sizeof(double), hipMemcpyDeviceToHost);
+    hipFree(d);
+    if (e != hipSuccess) return fail(TDG_EDEVICE, "rys rule: %s", hipGetErrorString(e));
+    return TDG_OK;
+}

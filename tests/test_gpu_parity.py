@@ -1,0 +1,163 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+FP64 bar: max-abs gradient difference <= 1e-8 hartree/bohr.  The two sides use
+different integral methods (Rys quadrature on the GPU, Obara-Saika/HGP on the
+CPU) and different summation orders; the difference observed is at rounding level.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from tests import molecules
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-8
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def tdg():
+    from paper_2407_16586_amd import tdgrad
+    tdgrad.lib()
+    return tdgrad
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ Rys rule
+def test_rys_rule_moments(tdg, oracle_lib):
+    """sum_i w_i u_i^k = F_k(T), k < 2n, for the device rule across the table's
+    intervals, their edges and the large-T branch (Boys values from the oracle,
+    itself pinned to mpmath)."""
+    Ts = [0.0, 1e-10, 0.3, 1.0, 1.999999, 2.0, 5.5, 13.0, 29.7, 40.0, 63.9999, 64.0, 64.5, 100.0, 1e3, 1e6]
+    for n in range(1, 6):
+        for T in Ts:
+            u, w = tdg.rys_rule(n, T)
+            F = oracle_lib.boys(2 * n - 1, T)
+            for k in range(2 * n):
+                mom = float(np.sum(w * u ** k))
+                assert abs(mom - F[k]) <= 1e-13 * F[k] + 1e-300, (n, T, k, mom, F[k])
+            assert np.all(np.diff(u) > 0) and np.all(u > 0) and np.all(u < 1)
+
+
+# ------------------------------------------------------------------ Schwarz
+def test_schwarz_factors(tdg, oracle_lib, mol0):
+    _say("schwarz config0")
+    p = tdg.Plan(mol0)
+    q_gpu = p.schwarz()
+    q_ref = oracle_lib.schwarz(mol0)
+    # Q enters only the screening bound; values below 1e-14 come from underflowing
+    # Gaussian-product factors.  Contracted integrals with mixed-sign coefficients lose
+    # a few digits to cancellation on both sides.
+    rel = np.abs(q_gpu - q_ref) / np.maximum(np.abs(q_ref), 1e-14)
+    k = int(np.argmax(rel))
+    _say("worst relative Q difference", rel[k], q_gpu[k], q_ref[k])
+    assert rel[k] <= 1e-9
+
+
+# ------------------------------------------------------------------ gradients
+@pytest.mark.parametrize("terms", [7, 1, 2, 4, 3])
+def test_config0_unscreened(tdg, oracle_lib, mol0, terms):
+    _say("config0 unscreened terms", terms)
+    p = tdg.Plan(mol0, schwarz_tol=0.0, terms=terms)
+    g, st = p.grad(mol0.P0, mol0.PD, mol0.R, stats=True)
+    ref, rst = oracle_lib.grad(mol0, terms=terms, return_stats=True)
+    err = np.abs(g - ref).max()
+    _say("  max-abs", err, "quartets", st["quartets"], rst["quartets"])
+    assert st["quartets"] == rst["quartets"]
+    assert st["prim_quartets"] == rst["prim_quartets"]
+    assert err <= TOL
+
+
+def test_config0_screened(tdg, oracle_lib, mol0):
+    _say("config0 screened")
+    p = tdg.Plan(mol0, schwarz_tol=1e-10)
+    g, st = p.grad(mol0.P0, mol0.PD, mol0.R, stats=True)
+    ref, rst = oracle_lib.grad(mol0, tau=1e-10, return_stats=True)
+    assert abs(st["quartets"] - rst["quartets"]) <= 2
+    assert np.abs(g - ref).max() <= TOL
+
+
+def test_small_mixed_all_classes(tdg, oracle_lib):
+    _say("small mixed")
+    m = molecules.small_mixed()
+    p = tdg.Plan(m, schwarz_tol=0.0)
+    g = p.grad(m.P0, m.PD, m.R)
+    ref = oracle_lib.grad(m)
+    assert np.abs(g - ref).max() <= TOL
+
+
+def test_translational_invariance(tdg, mol0):
+    p = tdg.Plan(mol0, schwarz_tol=0.0)
+    g = p.grad(mol0.P0, mol0.PD, mol0.R)
+    assert np.abs(g.sum(axis=0)).max() < 1e-9
+
+
+def test_single_atom_is_zero(tdg):
+    """One atom: every quartet is one-centre, the gradient is exactly zero."""
+    m = molecules.make([[0.1, 0.2, 0.3]], [(0, 0, [3.0, 0.5], [0.5, 0.6]), (0, 1, [1.0], [1.0]),
+                                           (0, 2, [0.8], [1.0])])
+    p = tdg.Plan(m, schwarz_tol=0.0)
+    g, st = p.grad(m.P0, m.PD, m.R, stats=True)
+    assert st["quartets"] == 0
+    assert np.all(g == 0.0)
+
+
+def test_s_only_and_global_hybrid(tdg, oracle_lib):
+    """Only s shells (one class), and beta = 0 (no long-range roots)."""
+    rng = np.random.default_rng(5)
+    coords = rng.uniform(-2, 2, (5, 3))
+    shells = [(a, 0, [4.0, 0.7], [0.4, 0.7]) for a in range(5)] + [(a, 0, [0.25], [1.0]) for a in range(5)]
+    m = molecules.make(coords, shells, seed=2)
+    for beta in (m.beta, 0.0):
+        p = tdg.Plan(m, schwarz_tol=0.0, beta=beta)
+        g = p.grad(m.P0, m.PD, m.R)
+        ref = oracle_lib.grad(m, beta=beta)
+        assert np.abs(g - ref).max() <= TOL
+
+
+def test_repeat_calls_and_new_densities(tdg, oracle_lib):
+    """A plan is reusable: later calls with other densities give the oracle's result."""
+    m = molecules.small_mixed(8)
+    p = tdg.Plan(m, schwarz_tol=0.0)
+    rng = np.random.default_rng(3)
+    for it in range(3):
+        n = m.n_bf
+        A = rng.standard_normal((n, n))
+        P0, PD, R = A @ A.T / n, 0.05 * (A + A.T), 0.2 * rng.standard_normal((n, n))
+        g = p.grad(P0, PD, R)
+        ref = oracle_lib.grad(m, P0=P0, PD=PD, R=R)
+        assert np.abs(g - ref).max() <= TOL, it
+
+
+def test_device_pointer_path(tdg, oracle_lib, mol0):
+    import torch
+    dev = torch.device("cuda:0")
+    p = tdg.Plan(mol0, schwarz_tol=1e-10)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    out = torch.zeros((mol0.n_atoms, 3), dtype=torch.float64, device=dev)
+    p.grad_device(t(mol0.P0), t(mol0.PD), t(mol0.R), out)
+    torch.cuda.synchronize()
+    ref = oracle_lib.grad(mol0, tau=1e-10)
+    assert np.abs(out.cpu().numpy() - ref).max() <= TOL
+
+
+def test_chain60_against_stored_oracle(tdg):
+    """Full 60-atom, 500-function chain at the production threshold 1e-10 against the
+    oracle's gradient stored by tests/golden/make_golden.py."""
+    from paper_2407_16586_amd import synth
+    path = os.path.join(HERE, "golden", "chain60_tau1e-10.json")
+    ref = json.load(open(path))
+    m = synth.config1()
+    _say("chain60 plan")
+    p = tdg.Plan(m, schwarz_tol=ref["tau"])
+    g, st = p.grad(m.P0, m.PD, m.R, stats=True)
+    err = np.abs(g - np.array(ref["grad"])).max()
+    _say("chain60 max-abs", err, "quartets", st["quartets"], ref["oracle_stats"]["quartets"])
+    assert abs(st["quartets"] - ref["oracle_stats"]["quartets"]) <= 0.0001 * ref["oracle_stats"]["quartets"]
+    assert err <= TOL
