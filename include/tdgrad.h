@@ -87,6 +87,10 @@ typedef struct {
     int32_t precision;  /* 0: FP64 throughout (the only value accepted so far) */
     int32_t terms;      /* bit 1: Coulomb-type (J) terms, bit 2: full-range exchange (alpha),
                            bit 4: long-range exchange (beta); 7 = all */
+    int32_t autotune;   /* 1: on the plan's first tdg_grad_jk call, time every kernel variant of
+                           each angular class on that call's tasks and keep the fastest */
+    int32_t kernel_variant; /* -1: per-class default or autotuned choice; 0: team-per-quartet
+                               kernels for every class; 1: wavefront-per-quartet kernels */
 } tdg_params_t;
 
 /* Per-call statistics (optional output). */
@@ -97,6 +101,7 @@ typedef struct {
     int64_t class_quartets[21];/* per angular class, in the library's class order */
     int64_t class_prim_quartets[21];
     double class_ms[21];       /* derivative-kernel time per class (HIP events on the call's stream) */
+    int32_t class_variant[21]; /* kernel variant used per class (0 team per quartet, 1 wave per quartet) */
     double ms_total;           /* wall time of the call (host clock, synchronised) */
     double ms_kernels;         /* summed derivative-kernel time (HIP events) */
 } tdg_stats_t;

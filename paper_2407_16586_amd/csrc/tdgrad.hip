@@ -25,6 +25,7 @@
 
 #include "../../include/tdgrad.h"
 #include "deriv_kernel.hpp"
+#include "deriv_wave.hpp"
 
 using namespace tdg;
 
@@ -134,6 +135,9 @@ struct tdg_plan {
     std::vector<int> item_class_off;       // [22] offset of each class's items
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ev_cls[kNumClasses + 1] = {};
+    int variant[kNumClasses];              // kernel variant per class (0 team-per-quartet, 1 wave-per-quartet)
+    bool tuned = false;                    // variants measured on this plan's first call
+    DevBuf<double> d_grad_tune;            // scratch gradient for the tuning launches
 };
 
 // ======================================================================= a1
@@ -365,47 +369,65 @@ __global__ void k_zero(double *p, long long n)
 
 // ======================================================================= dispatch
 template <int LA, int LB, int LC, int LD, bool LR>
-static hipError_t launch_one(const DerivArgs &a, hipStream_t st, int grid_max)
+static hipError_t launch_one(int variant, const DerivArgs &a, hipStream_t st, int grid_max)
 {
-    using K = DerivClass<LA, LB, LC, LD, LR>;
-    const long long blocks_needed = (a.ntasks + K::TPB - 1) / K::TPB;
-    const int grid = (int)std::min<long long>(blocks_needed, grid_max);
     const size_t dyn = a.lds_atoms ? (size_t)3 * a.n_atoms * sizeof(double) : 0;
-    hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+    if (variant == 0) {
+        using K = DerivClass<LA, LB, LC, LD, LR>;
+        const long long blocks_needed = (a.ntasks + K::TPB - 1) / K::TPB;
+        const int grid = (int)std::min<long long>(blocks_needed, grid_max);
+        hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+    } else {
+        using K = WaveClass<LA, LB, LC, LD, LR>;
+        const long long blocks_needed = (a.ntasks + K::WAVES - 1) / K::WAVES;
+        const int grid = (int)std::min<long long>(blocks_needed, grid_max);
+        hipLaunchKernelGGL((k_deriv_wave<LA, LB, LC, LD, LR>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+    }
     return hipGetLastError();
 }
 
 template <int LA, int LB, int LC, int LD>
-static hipError_t launch_lr(const DerivArgs &a, bool lr, hipStream_t st, int grid_max)
+static hipError_t launch_lr(int variant, const DerivArgs &a, bool lr, hipStream_t st, int grid_max)
 {
-    return lr ? launch_one<LA, LB, LC, LD, true>(a, st, grid_max) : launch_one<LA, LB, LC, LD, false>(a, st, grid_max);
+    return lr ? launch_one<LA, LB, LC, LD, true>(variant, a, st, grid_max)
+              : launch_one<LA, LB, LC, LD, false>(variant, a, st, grid_max);
 }
 
-static hipError_t launch_class(int c, const DerivArgs &a, bool lr, hipStream_t st, int grid_max)
+static hipError_t launch_class(int c, int variant, const DerivArgs &a, bool lr, hipStream_t st, int grid_max)
 {
     switch (c) {
-    case 0: return launch_lr<0, 0, 0, 0>(a, lr, st, grid_max);
-    case 1: return launch_lr<1, 0, 0, 0>(a, lr, st, grid_max);
-    case 2: return launch_lr<1, 0, 1, 0>(a, lr, st, grid_max);
-    case 3: return launch_lr<1, 1, 0, 0>(a, lr, st, grid_max);
-    case 4: return launch_lr<1, 1, 1, 0>(a, lr, st, grid_max);
-    case 5: return launch_lr<1, 1, 1, 1>(a, lr, st, grid_max);
-    case 6: return launch_lr<2, 0, 0, 0>(a, lr, st, grid_max);
-    case 7: return launch_lr<2, 0, 1, 0>(a, lr, st, grid_max);
-    case 8: return launch_lr<2, 0, 1, 1>(a, lr, st, grid_max);
-    case 9: return launch_lr<2, 0, 2, 0>(a, lr, st, grid_max);
-    case 10: return launch_lr<2, 1, 0, 0>(a, lr, st, grid_max);
-    case 11: return launch_lr<2, 1, 1, 0>(a, lr, st, grid_max);
-    case 12: return launch_lr<2, 1, 1, 1>(a, lr, st, grid_max);
-    case 13: return launch_lr<2, 1, 2, 0>(a, lr, st, grid_max);
-    case 14: return launch_lr<2, 1, 2, 1>(a, lr, st, grid_max);
-    case 15: return launch_lr<2, 2, 0, 0>(a, lr, st, grid_max);
-    case 16: return launch_lr<2, 2, 1, 0>(a, lr, st, grid_max);
-    case 17: return launch_lr<2, 2, 1, 1>(a, lr, st, grid_max);
-    case 18: return launch_lr<2, 2, 2, 0>(a, lr, st, grid_max);
-    case 19: return launch_lr<2, 2, 2, 1>(a, lr, st, grid_max);
-    default: return launch_lr<2, 2, 2, 2>(a, lr, st, grid_max);
+    case 0: return launch_lr<0, 0, 0, 0>(variant, a, lr, st, grid_max);
+    case 1: return launch_lr<1, 0, 0, 0>(variant, a, lr, st, grid_max);
+    case 2: return launch_lr<1, 0, 1, 0>(variant, a, lr, st, grid_max);
+    case 3: return launch_lr<1, 1, 0, 0>(variant, a, lr, st, grid_max);
+    case 4: return launch_lr<1, 1, 1, 0>(variant, a, lr, st, grid_max);
+    case 5: return launch_lr<1, 1, 1, 1>(variant, a, lr, st, grid_max);
+    case 6: return launch_lr<2, 0, 0, 0>(variant, a, lr, st, grid_max);
+    case 7: return launch_lr<2, 0, 1, 0>(variant, a, lr, st, grid_max);
+    case 8: return launch_lr<2, 0, 1, 1>(variant, a, lr, st, grid_max);
+    case 9: return launch_lr<2, 0, 2, 0>(variant, a, lr, st, grid_max);
+    case 10: return launch_lr<2, 1, 0, 0>(variant, a, lr, st, grid_max);
+    case 11: return launch_lr<2, 1, 1, 0>(variant, a, lr, st, grid_max);
+    case 12: return launch_lr<2, 1, 1, 1>(variant, a, lr, st, grid_max);
+    case 13: return launch_lr<2, 1, 2, 0>(variant, a, lr, st, grid_max);
+    case 14: return launch_lr<2, 1, 2, 1>(variant, a, lr, st, grid_max);
+    case 15: return launch_lr<2, 2, 0, 0>(variant, a, lr, st, grid_max);
+    case 16: return launch_lr<2, 2, 1, 0>(variant, a, lr, st, grid_max);
+    case 17: return launch_lr<2, 2, 1, 1>(variant, a, lr, st, grid_max);
+    case 18: return launch_lr<2, 2, 2, 0>(variant, a, lr, st, grid_max);
+    case 19: return launch_lr<2, 2, 2, 1>(variant, a, lr, st, grid_max);
+    default: return launch_lr<2, 2, 2, 2>(variant, a, lr, st, grid_max);
     }
+}
+
+// default variant before measurement: the wave-per-quartet kernel for classes whose
+// per-lane register tables would not fit (N >= 81 Cartesian components)
+static int default_variant(int c)
+{
+    int pb, pk;
+    class_pk(c, pb, pk);
+    const int n = ncart(kPairL[pb][0]) * ncart(kPairL[pb][1]) * ncart(kPairL[pk][0]) * ncart(kPairL[pk][1]);
+    return n >= 81 ? 1 : 0;
 }
 
 template <int LA, int LB>
@@ -607,6 +629,8 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
     HIP_TRY(hipEventCreate(&pl->ev0));
     HIP_TRY(hipEventCreate(&pl->ev1));
     for (auto &e : pl->ev_cls) HIP_TRY(hipEventCreate(&e));
+    for (int c = 0; c < kNumClasses; ++c)
+        pl->variant[c] = pl->prm.kernel_variant >= 0 ? pl->prm.kernel_variant : default_variant(c);
     HIP_TRY(hipDeviceSynchronize());
     return TDG_OK;
 }
@@ -645,6 +669,8 @@ int tdg_plan_create(const tdg_basis_t *basis, const tdg_params_t *params, int de
     if (rc) return rc;
     if (params->precision != 0) return fail(TDG_EUNSUPPORTED, "precision mode %d not available", params->precision);
     if ((params->terms & 4) && !(params->omega > 0.0)) return fail(TDG_EINVAL, "long-range term needs omega > 0");
+    if (params->kernel_variant < -1 || params->kernel_variant > 1)
+        return fail(TDG_EINVAL, "kernel_variant must be -1, 0 or 1");
     int ndev = 0;
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(TDG_EINVAL, "device %d not present (%d devices)", device, ndev);
@@ -676,6 +702,7 @@ int tdg_plan_destroy(tdg_plan_t *pl)
     pl->d_item_off.release();
     pl->d_prim_cnt.release();
     pl->d_cand_cnt.release();
+    pl->d_grad_tune.release();
     for (auto &e : pl->ev_cls)
         if (e) hipEventDestroy(e);
     pl->d_mx.release();
@@ -815,6 +842,32 @@ int tdg_grad_jk(tdg_plan_t *pl, const double *P0, const double *PD, const double
         if (hipGetDeviceProperties(&prop, pl->device) == hipSuccess) ncu = prop.multiProcessorCount;
     }
     const int grid_max = ncu * 8;
+    if (pl->prm.autotune && pl->prm.kernel_variant < 0 && !pl->tuned) {
+        // a12 autotuner: time every kernel variant of each class on this call's task list
+        // (into a scratch gradient), keep the fastest for the plan's later calls
+        if ((rc = pl->d_grad_tune.alloc((size_t)3 * pl->n_atoms))) return rc;
+        DerivArgs at = a;
+        at.grad = pl->d_grad_tune.p;
+        for (int c = 0; c < kNumClasses; ++c) {
+            const long long n = class_begin[c + 1] - class_begin[c];
+            if (!n) continue;
+            at.tasks = pl->d_tasks.p + class_begin[c];
+            at.ntasks = n;
+            float best = 1e30f;
+            for (int v = 0; v < 2; ++v) {
+                float ms = 0.f;
+                for (int rep = 0; rep < 2; ++rep) { // second launch is the measured one
+                    HIP_TRY(hipEventRecord(pl->ev_cls[0], st));
+                    HIP_TRY(launch_class(c, v, at, lr, st, grid_max));
+                    HIP_TRY(hipEventRecord(pl->ev_cls[1], st));
+                    HIP_TRY(hipEventSynchronize(pl->ev_cls[1]));
+                    HIP_TRY(hipEventElapsedTime(&ms, pl->ev_cls[0], pl->ev_cls[1]));
+                }
+                if (ms < best) { best = ms; pl->variant[c] = v; }
+            }
+        }
+        pl->tuned = true;
+    }
     HIP_TRY(hipEventRecord(pl->ev0, st));
     for (int c = 0; c < kNumClasses; ++c) {
         HIP_TRY(hipEventRecord(pl->ev_cls[c], st));
@@ -822,7 +875,7 @@ int tdg_grad_jk(tdg_plan_t *pl, const double *P0, const double *PD, const double
         if (!n) continue;
         a.tasks = pl->d_tasks.p + class_begin[c];
         a.ntasks = n;
-        HIP_TRY(launch_class(c, a, lr, st, grid_max));
+        HIP_TRY(launch_class(c, pl->variant[c], a, lr, st, grid_max));
     }
     HIP_TRY(hipEventRecord(pl->ev_cls[kNumClasses], st));
     HIP_TRY(hipEventRecord(pl->ev1, st));
@@ -843,6 +896,7 @@ int tdg_grad_jk(tdg_plan_t *pl, const double *P0, const double *PD, const double
             float cm = 0.f;
             HIP_TRY(hipEventElapsedTime(&cm, pl->ev_cls[c], pl->ev_cls[c + 1]));
             stats->class_ms[c] = cm;
+            stats->class_variant[c] = pl->variant[c];
         }
         stats->quartets = total;
         float ms = 0.f;

@@ -41,21 +41,24 @@ class Basis(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("omega", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
-                ("schwarz_tol", C.c_double), ("precision", C.c_int32), ("terms", C.c_int32)]
+                ("schwarz_tol", C.c_double), ("precision", C.c_int32), ("terms", C.c_int32),
+                ("autotune", C.c_int32), ("kernel_variant", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("quartets", C.c_int64), ("prim_quartets", C.c_int64), ("candidates", C.c_int64),
                 ("class_quartets", C.c_int64 * NUM_CLASSES),
                 ("class_prim_quartets", C.c_int64 * NUM_CLASSES),
-                ("class_ms", C.c_double * NUM_CLASSES), ("ms_total", C.c_double),
+                ("class_ms", C.c_double * NUM_CLASSES),
+                ("class_variant", C.c_int32 * NUM_CLASSES), ("ms_total", C.c_double),
                 ("ms_kernels", C.c_double)]
 
     def as_dict(self):
         return {"quartets": self.quartets, "prim_quartets": self.prim_quartets,
                 "candidates": self.candidates, "class_quartets": list(self.class_quartets),
                 "class_prim_quartets": list(self.class_prim_quartets),
-                "class_ms": list(self.class_ms), "ms_total": self.ms_total,
+                "class_ms": list(self.class_ms), "class_variant": list(self.class_variant),
+                "ms_total": self.ms_total,
                 "ms_kernels": self.ms_kernels}
 
 
@@ -99,7 +102,7 @@ class Plan:
     """A plan for one molecule (geometry + basis); see tdg_plan_create."""
 
     def __init__(self, mol, omega=None, alpha=None, beta=None, schwarz_tol=1e-10, terms=TERMS_ALL,
-                 precision=0, device=0):
+                 precision=0, device=0, autotune=True, kernel_variant=-1):
         self._keep = [np.ascontiguousarray(mol.coords, dtype=np.float64)]
         for name in ("shell_atom", "shell_l", "shell_nprim", "shell_prim_off", "shell_ao_off"):
             self._keep.append(np.ascontiguousarray(getattr(mol, name), dtype=np.int32))
@@ -109,7 +112,8 @@ class Plan:
         b = Basis(mol.n_atoms, _ptr(k[0]), mol.n_shells, _ptr(k[1]), _ptr(k[2]), _ptr(k[3]),
                   _ptr(k[4]), _ptr(k[5]), mol.n_prims, _ptr(k[6]), _ptr(k[7]))
         self.params = Params(mol.omega if omega is None else omega, mol.alpha if alpha is None else alpha,
-                             mol.beta if beta is None else beta, schwarz_tol, precision, terms)
+                             mol.beta if beta is None else beta, schwarz_tol, precision, terms,
+                             1 if autotune else 0, kernel_variant)
         h = C.c_void_p()
         _check(lib().tdg_plan_create(C.byref(b), C.byref(self.params), device, C.byref(h)))
         self._h = h

@@ -147,7 +147,8 @@ def test_device_pointer_path(tdg, oracle_lib, mol0):
     assert np.abs(out.cpu().numpy() - ref).max() <= TOL
 
 
-def test_chain60_against_stored_oracle(tdg):
+@pytest.mark.parametrize("variant", [-1, 1])
+def test_chain60_against_stored_oracle(tdg, variant):
     """Full 60-atom, 500-function chain at the production threshold 1e-10 against the
     oracle's gradient stored by tests/golden/make_golden.py."""
     from paper_2407_16586_amd import synth
@@ -155,9 +156,37 @@ def test_chain60_against_stored_oracle(tdg):
     ref = json.load(open(path))
     m = synth.config1()
     _say("chain60 plan")
-    p = tdg.Plan(m, schwarz_tol=ref["tau"])
+    p = tdg.Plan(m, schwarz_tol=ref["tau"], kernel_variant=variant)
     g, st = p.grad(m.P0, m.PD, m.R, stats=True)
     err = np.abs(g - np.array(ref["grad"])).max()
     _say("chain60 max-abs", err, "quartets", st["quartets"], ref["oracle_stats"]["quartets"])
     assert abs(st["quartets"] - ref["oracle_stats"]["quartets"]) <= 0.0001 * ref["oracle_stats"]["quartets"]
     assert err <= TOL
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_both_kernel_variants_all_classes(tdg, oracle_lib, mol0, variant):
+    """Each of the two kernel designs (team per quartet, wavefront per quartet), forced on
+    every angular class, matches the oracle."""
+    _say("variant", variant)
+    for m in (mol0, molecules.small_mixed()):
+        p = tdg.Plan(m, schwarz_tol=0.0, kernel_variant=variant)
+        g, st = p.grad(m.P0, m.PD, m.R, stats=True)
+        assert all(v == variant for v, n in zip(st["class_variant"], st["class_quartets"]) if n)
+        ref = oracle_lib.grad(m)
+        err = np.abs(g - ref).max()
+        _say("  max-abs", err)
+        assert err <= TOL
+    m = molecules.small_mixed()
+    p = tdg.Plan(m, schwarz_tol=0.0, kernel_variant=variant, beta=0.0, terms=3)
+    assert np.abs(p.grad(m.P0, m.PD, m.R) - oracle_lib.grad(m, beta=0.0, terms=3)).max() <= TOL
+
+
+def test_autotuned_plan_is_stable(tdg, mol0, oracle_lib):
+    """The first call tunes the variants; later calls reuse them and give the same result."""
+    p = tdg.Plan(mol0, schwarz_tol=1e-10, autotune=True)
+    g1, s1 = p.grad(mol0.P0, mol0.PD, mol0.R, stats=True)
+    g2, s2 = p.grad(mol0.P0, mol0.PD, mol0.R, stats=True)
+    assert s1["class_variant"] == s2["class_variant"]
+    assert np.abs(g1 - g2).max() <= 1e-12
+    assert np.abs(g2 - oracle_lib.grad(mol0, tau=1e-10)).max() <= TOL
