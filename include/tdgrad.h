@@ -58,6 +58,7 @@ typedef enum {
 } tdg_status;
 
 typedef struct tdg_plan tdg_plan_t; /* opaque */
+typedef struct tdg_mlp tdg_mlp_t;   /* opaque: quartet-contribution estimator */
 
 /* Basis and geometry (host pointers, copied by tdg_plan_create). */
 typedef struct {
@@ -84,13 +85,21 @@ typedef struct {
     double alpha;       /* full-range exchange fraction */
     double beta;        /* long-range exchange fraction */
     double schwarz_tol; /* skip a quartet when Q_ab Q_cd M_abcd < schwarz_tol; 0 = no screening */
-    int32_t precision;  /* 0: FP64 throughout (the only value accepted so far) */
+    int32_t precision;  /* 0: FP64 throughout; 1: mixed -- 2D integrals, derivative products and
+                           per-primitive partial sums in FP32 for quartets routed to FP32; Rys
+                           roots, weights, prefactors and all accumulation in FP64.  A quartet
+                           is routed to FP32 when bound * f_ab * f_cd < mixed_tau64 and every
+                           primitive exponent sum is < mixed_p64, with f the pair's FP32
+                           error-amplification factor max_k (1 + |AB| zeta_b/sqrt(p))^(lb+1)
+                           sqrt(max zeta) over its primitive pairs */
     int32_t terms;      /* bit 1: Coulomb-type (J) terms, bit 2: full-range exchange (alpha),
                            bit 4: long-range exchange (beta); 7 = all */
     int32_t autotune;   /* 1: on the plan's first tdg_grad_jk call, time every kernel variant of
                            each angular class on that call's tasks and keep the fastest */
     int32_t kernel_variant; /* -1: per-class default or autotuned choice; 0: team-per-quartet
                                kernels for every class; 1: wavefront-per-quartet kernels */
+    double mixed_tau64; /* mixed mode: FP32 only when bound * f_ab * f_cd is below this */
+    double mixed_p64;   /* mixed mode: pairs with a primitive exponent sum >= this stay FP64 */
 } tdg_params_t;
 
 /* Per-call statistics (optional output). */
@@ -101,7 +110,11 @@ typedef struct {
     int64_t class_quartets[21];/* per angular class, in the library's class order */
     int64_t class_prim_quartets[21];
     double class_ms[21];       /* derivative-kernel time per class (HIP events on the call's stream) */
-    int32_t class_variant[21]; /* kernel variant used per class (0 team per quartet, 1 wave per quartet) */
+    int32_t class_variant[21]; /* kernel variants per class: bit 0 the FP64 list's, bit 1 the FP32 list's
+                                  (0 team per quartet, 1 wavefront per quartet) */
+    int64_t fp32_quartets;     /* mixed mode: quartets evaluated with FP32 2D integrals */
+    int64_t ml_skipped;        /* quartets vetoed by the contribution estimator */
+    int64_t class_fp32_quartets[21];
     double ms_total;           /* wall time of the call (host clock, synchronised) */
     double ms_kernels;         /* summed derivative-kernel time (HIP events) */
 } tdg_stats_t;
@@ -122,6 +135,58 @@ int tdg_plan_create(const tdg_basis_t *basis, const tdg_params_t *params, int de
  * Errors: TDG_EINVAL, TDG_ENOMEM, TDG_EDEVICE, TDG_ESTATE. */
 int tdg_grad_jk(tdg_plan_t *plan, const double *P0, const double *PDelta, const double *R,
                 int32_t ptr_kind, void *hip_stream, double *grad, tdg_stats_t *stats);
+
+/* Gradients of n molecules in one pass: per molecule density preparation and
+ * screening, then one launch per angular class and precision over all the
+ * molecules' quartets (a persistent grid striding over the concatenated task
+ * lists).  plans[m] with densities P0[m], PDelta[m], R[m] writes grad[m]
+ * ([n_atoms(m)][3]).  All plans must share device, omega, alpha, beta, terms and
+ * precision, and appear once.  Work buffers of the batch belong to plans[0]; its
+ * autotuned variants for batched calls are kept separately from single calls.
+ * Errors: as tdg_grad_jk. */
+int tdg_grad_jk_batch(int32_t n, tdg_plan_t *const *plans, const double *const *P0,
+                      const double *const *PDelta, const double *const *R, int32_t ptr_kind,
+                      void *hip_stream, double *const *grad, tdg_stats_t *stats);
+
+/* ---------------------------------------------------------------------------
+ * Learned screening.  A 10 -> 64 -> 64 -> 1 ReLU network predicts, from features of
+ * a shell quartet that passed the density-multiplied Schwarz bound (log Q_ab,
+ * log Q_cd, log of the density-block product, extreme primitive exponent sums of
+ * both pairs, pair distance, angular momentum, bond lengths), log10 of the largest
+ * of its twelve gradient contributions (scaled by 1/10).  Forward and backward
+ * passes use BF16 matrix-core instructions with FP32 accumulation; weights are
+ * FP32 (tdg_mlp_nweights() floats: W1[64][16], b1[64], W2[64][64], b2[64],
+ * W3[64], b3).  Used as a veto on top of the Schwarz screening, for the callers
+ * that train it on contributions this library generates (tdg_collect).
+ * ------------------------------------------------------------------------- */
+int tdg_mlp_create(int device, uint64_t seed, tdg_mlp_t **out);   /* seeded initial weights */
+int tdg_mlp_destroy(tdg_mlp_t *model);
+int tdg_mlp_nweights(void);
+int tdg_mlp_set_weights(tdg_mlp_t *model, const float *w_host);   /* resets the Adam state */
+int tdg_mlp_get_weights(const tdg_mlp_t *model, float *w_host);
+/* predictions for n samples: X device [n][16] FP32, out device [n] FP32 (async on stream) */
+int tdg_mlp_forward(const tdg_mlp_t *model, const float *X, int64_t n, float *out, void *hip_stream);
+/* loss mean((pred - Y)^2) and its gradient (host [nweights]) for n device samples; no update */
+int tdg_mlp_grad(tdg_mlp_t *model, const float *X, const float *Y, int64_t n, float *grad_host,
+                 float *loss_host, void *hip_stream);
+/* one Adam step (beta 0.9/0.999) on a batch of n device samples; loss_host may be NULL */
+int tdg_mlp_train_step(tdg_mlp_t *model, const float *X, const float *Y, int64_t n, float lr,
+                       float *loss_host, void *hip_stream);
+
+/* Attach an estimator to a plan (NULL detaches): a screened quartet is skipped when the
+ * predicted log10 contribution is below log10_threshold and its screening bound is below
+ * tau_hi (the rigorous bound keeps large quartets).  The model must outlive its use.
+ * Applies to tdg_grad_jk (not to batched calls). */
+int tdg_plan_set_screen_model(tdg_plan_t *plan, const tdg_mlp_t *model, double log10_threshold,
+                              double tau_hi);
+
+/* Training data generated by the method itself: screens the quartets of one FP64 plan,
+ * evaluates every surviving quartet's twelve gradient contributions, and writes features
+ * (device [cap][16]) and targets (device [cap], log10 of the largest contribution / 10)
+ * of every stride-th surviving quartet; *n_out = samples written (<= cap). */
+int tdg_collect(tdg_plan_t *plan, const double *P0, const double *PDelta, const double *R,
+                int32_t ptr_kind, void *hip_stream, float *feat, float *target, int64_t cap,
+                int64_t stride, int64_t *n_out);
 
 /* Release a plan and its device memory (NULL is accepted). */
 int tdg_plan_destroy(tdg_plan_t *plan);

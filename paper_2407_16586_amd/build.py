@@ -10,8 +10,9 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtdgrad.so")
 TABLE = os.path.join(CSRC, "rys_table.inc")
 GEN = os.path.join(CSRC, "gen_rys_table.py")
-SOURCES = [os.path.join(CSRC, "tdgrad.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("tdg_device.hpp", "deriv_kernel.hpp")]
+MAIN = os.path.join(CSRC, "tdgrad.hip")
+CLASS_SRC = os.path.join(CSRC, "class_kernels.hip")
+NUM_CLASSES = 21
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
@@ -27,15 +28,40 @@ def table(force: bool = False) -> str:
     return TABLE
 
 
-def build(extra_flags: list[str] | None = None, verbose: bool = False) -> str:
+def build(extra_flags: list[str] | None = None, verbose: bool = False, jobs: int | None = None) -> str:
+    """Compile the host runtime and the 21 per-class kernel units in parallel, then link."""
+    import concurrent.futures as cf
+    import tempfile
+
     table()
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *(extra_flags or []), "-o", tmp, *SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd, cwd=CSRC)
-    os.replace(tmp, LIB)
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"] + list(extra_flags or [])
+    with tempfile.TemporaryDirectory(prefix="tdgrad_build_") as tmpd:
+        jobs_ = [(MAIN, os.path.join(tmpd, "tdgrad.o"), []),
+                 (os.path.join(CSRC, "mlp.hip"), os.path.join(tmpd, "mlp.o"), [])]
+        for c in range(NUM_CLASSES):
+            jobs_.append((CLASS_SRC, os.path.join(tmpd, f"class_{c}.o"), [f"-DTDG_CLASS={c}"]))
+
+        def compile_one(job):
+            src, obj, defs = job
+            cmd = [hipcc, *flags, *defs, "-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            r = subprocess.run(cmd, cwd=CSRC, capture_output=True, text=True)
+            return r.returncode, r.stdout + r.stderr, obj
+
+        n = jobs or min(len(jobs_), max(1, min(16, os.cpu_count() or 1)))
+        with cf.ThreadPoolExecutor(n) as ex:
+            results = list(ex.map(compile_one, jobs_))
+        for rc, out, obj in results:
+            if verbose or rc:
+                sys.stderr.write(out)
+            if rc:
+                raise RuntimeError(f"compilation of {obj} failed")
+        tmp = LIB + ".tmp"
+        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [r[2] for r in results]
+        subprocess.check_call(cmd, cwd=CSRC)
+        os.replace(tmp, LIB)
     return LIB
 
 

@@ -1,0 +1,57 @@
+// Kernels of one angular class (la lb|lc ld), selected by -DTDG_CLASS=c in the
+// library's class order: bra pair class PB >= ket pair class PK over the pair
+// classes (ss, ps, pp, ds, dp, dd), the highest momentum on centre A.
+#include "class_launch.hpp"
+#include "deriv_wave.hpp"
+
+#ifndef TDG_CLASS
+#error "compile with -DTDG_CLASS=<0..20>"
+#endif
+
+namespace {
+constexpr int kPL[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
+constexpr int class_pb(int c)
+{
+    int k = 0;
+    for (int b = 0; b < 6; ++b)
+        for (int q = 0; q <= b; ++q, ++k)
+            if (k == c) return b;
+    return -1;
+}
+constexpr int class_pk(int c)
+{
+    int k = 0;
+    for (int b = 0; b < 6; ++b)
+        for (int q = 0; q <= b; ++q, ++k)
+            if (k == c) return q;
+    return -1;
+}
+constexpr int LA = kPL[class_pb(TDG_CLASS)][0], LB = kPL[class_pb(TDG_CLASS)][1];
+constexpr int LC = kPL[class_pk(TDG_CLASS)][0], LD = kPL[class_pk(TDG_CLASS)][1];
+
+template <bool LR, typename F>
+hipError_t go(int variant, const tdg::DerivArgs &a, hipStream_t st, int grid_max)
+{
+    using namespace tdg;
+    const size_t dyn = a.lds_atoms ? (size_t)3 * a.n_atoms * sizeof(double) : 0;
+    if (variant == 0) {
+        using K = DerivClass<LA, LB, LC, LD, LR, F>;
+        const long long blocks = (a.ntasks + K::TPB - 1) / K::TPB;
+        const int grid = (int)(blocks < grid_max ? blocks : grid_max);
+        hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+    } else {
+        using K = WaveClass<LA, LB, LC, LD, LR, F>;
+        const long long blocks = (a.ntasks + K::WAVES - 1) / K::WAVES;
+        const int grid = (int)(blocks < grid_max ? blocks : grid_max);
+        hipLaunchKernelGGL((k_deriv_wave<LA, LB, LC, LD, LR, F>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+    }
+    return hipGetLastError();
+}
+} // namespace
+
+hipError_t TDG_LAUNCH_NAME(TDG_CLASS)(int variant, int prec, const tdg::DerivArgs &a, bool lr, hipStream_t st,
+                                      int grid_max)
+{
+    if (prec) return lr ? go<true, float>(variant, a, st, grid_max) : go<false, float>(variant, a, st, grid_max);
+    return lr ? go<true, double>(variant, a, st, grid_max) : go<false, double>(variant, a, st, grid_max);
+}

@@ -22,35 +22,38 @@ struct DerivArgs {
     int n_atoms;
     int lds_atoms;          // 1: block-level accumulation in LDS (dynamic shared memory)
     double *task_out;       // optional per-task output [ntasks][12] (canonical centres)
+    // batched launch over many molecules: per-task molecule index and per-molecule
+    // argument blocks (their own tables, densities and gradient); null for one molecule
+    const int *task_mol;
+    const DerivArgs *batch;
 };
 
 // 2D Rys integrals for one root and one Cartesian direction.
 // Vertical recursion on centres A (bra) and C (ket) up to n <= NM, m <= MM, then
 // horizontal transfer A->B (j <= JE) and C->D (l <= LE).  Entry X[i][j][k][l] is
 // defined for i <= IE, j <= JE, k + l <= MM with k <= MM - l.
-template <int NM, int MM, int IE, int JE, int LE>
+template <int NM, int MM, int IE, int JE, int LE, typename F = double>
 struct Rys2D {
-    double X[IE + 1][JE + 1][MM + 1][LE + 1];
+    F X[IE + 1][JE + 1][MM + 1][LE + 1];
 
-    __device__ __forceinline__ void build(double I0, double C00, double D00, double B10, double B01,
-                                          double B00, double AB, double CD)
+    __device__ __forceinline__ void build(F I0, F C00, F D00, F B10, F B01, F B00, F AB, F CD)
     {
-        double V[NM + 1][MM + 1];
+        F V[NM + 1][MM + 1];
         V[0][0] = I0;
         if constexpr (NM >= 1) V[1][0] = C00 * I0;
 #pragma unroll
-        for (int n = 1; n < NM; ++n) V[n + 1][0] = C00 * V[n][0] + (n * B10) * V[n - 1][0];
+        for (int n = 1; n < NM; ++n) V[n + 1][0] = C00 * V[n][0] + (F(n) * B10) * V[n - 1][0];
 #pragma unroll
         for (int m = 0; m < MM; ++m) {
 #pragma unroll
             for (int n = 0; n <= NM; ++n) {
-                double v = D00 * V[n][m];
-                if (m > 0) v += (m * B01) * V[n][m > 0 ? m - 1 : 0];
-                if (n > 0) v += (n * B00) * V[n > 0 ? n - 1 : 0][m];
+                F v = D00 * V[n][m];
+                if (m > 0) v += (F(m) * B01) * V[n][m > 0 ? m - 1 : 0];
+                if (n > 0) v += (F(n) * B00) * V[n > 0 ? n - 1 : 0][m];
                 V[n][m + 1] = v;
             }
         }
-        double W[NM + 1][JE + 1][MM + 1];
+        F W[NM + 1][JE + 1][MM + 1];
 #pragma unroll
         for (int i = 0; i <= NM; ++i)
 #pragma unroll
@@ -78,7 +81,107 @@ struct Rys2D {
     }
 };
 
-template <int LA, int LB, int LC, int LD, bool LR>
+// Direct four-centre form used for the FP32 route.  The 2D integrals over the base
+// index range (i<=la, j<=lb, k<=lc, l<=ld) are built by raising each index with its
+// own centre's displacement,
+//   I(.., x+1, ..) = C_X I + B10 [i I(i-1) + j I(j-1)] + B00 [k I(k-1) + l I(l-1)]   (x = i, j)
+//   I(.., x+1, ..) = C_X I + B01 [k I(k-1) + l I(l-1)] + B00 [i I(i-1) + j I(j-1)]   (x = k, l)
+// with C_A = (P-A) - rho/p PQ u, C_B = (P-B) - rho/p PQ u, C_C = (Q-C) + rho/q PQ u,
+// C_D = (Q-D) + rho/q PQ u, so no step transfers momentum across a bond (no
+// A->B difference of large terms).  The centre derivatives 2 zeta X(+1) - n X(-1) are
+// expanded with the same recurrence, e.g.
+//   dB = 2 zb C_B I + 2 zb B10 i I(i-1) + (2 zb B10 - 1) j I(j-1) + 2 zb B00 (k I(k-1) + l I(l-1)),
+// whose coefficients (2 zb B10 - 1 = -za/p - zb q u/(p(p+q)) and its C, D analogues) are
+// formed in FP64 without cancellation.
+struct DirectCoef {
+    double e2, e3, e4, f2, f3, f4, g2, g3, g4; // direction-independent derivative coefficients
+};
+
+__device__ __forceinline__ DirectCoef direct_coef(double za, double zb, double zc, double zd, double p, double q,
+                                                  double u, double ipq, double B10, double B01, double B00)
+{
+    DirectCoef c;
+    c.e2 = 2.0 * zb * B10;
+    c.e3 = -za / p - zb * q * u * ipq / p;
+    c.e4 = 2.0 * zb * B00;
+    c.f2 = -zd / q - zc * p * u * ipq / q;
+    c.f3 = 2.0 * zc * B01;
+    c.f4 = 2.0 * zc * B00;
+    c.g2 = 2.0 * zd * B01;
+    c.g3 = -zc / q - zd * p * u * ipq / q;
+    c.g4 = 2.0 * zd * B00;
+    return c;
+}
+
+// out[0][e] = I, out[1][e] = dB, out[2][e] = dC, out[3][e] = dD for the base index
+// e = ((i*(lb+1)+j)*(lc+1)+k)*(ld+1)+l; stride between the four kinds is NBASE.
+template <int LA, int LB, int LC, int LD, typename F, typename OUT>
+__device__ __forceinline__ void direct_tables(OUT &out, F I0, F CA, F CB, F CC, F CDd, F B10, F B01, F B00, F e1, F e2,
+                                              F e3, F e4, F f1, F f2, F f3, F f4, F g1, F g2, F g3, F g4)
+{
+    constexpr int NB1 = LB + 1, NC1 = LC + 1, ND1 = LD + 1;
+    constexpr int NBASE = (LA + 1) * NB1 * NC1 * ND1;
+    F I[NBASE];
+#define IX(i, j, k, l) I[(((i) * NB1 + (j)) * NC1 + (k)) * ND1 + (l)]
+#pragma unroll
+    for (int i = 0; i <= LA; ++i)
+#pragma unroll
+        for (int j = 0; j <= LB; ++j)
+#pragma unroll
+            for (int k = 0; k <= LC; ++k)
+#pragma unroll
+                for (int l = 0; l <= LD; ++l) {
+                    F v;
+                    if (l > 0) {
+                        const int l0 = l - 1;
+                        v = CDd * IX(i, j, k, l0);
+                        if (k > 0) v += F(k) * B01 * IX(i, j, k > 0 ? k - 1 : 0, l0);
+                        if (l0 > 0) v += F(l0) * B01 * IX(i, j, k, l0 > 0 ? l0 - 1 : 0);
+                        if (i > 0) v += F(i) * B00 * IX(i > 0 ? i - 1 : 0, j, k, l0);
+                        if (j > 0) v += F(j) * B00 * IX(i, j > 0 ? j - 1 : 0, k, l0);
+                    } else if (k > 0) {
+                        const int k0 = k - 1;
+                        v = CC * IX(i, j, k0, 0);
+                        if (k0 > 0) v += F(k0) * B01 * IX(i, j, k0 > 0 ? k0 - 1 : 0, 0);
+                        if (i > 0) v += F(i) * B00 * IX(i > 0 ? i - 1 : 0, j, k0, 0);
+                        if (j > 0) v += F(j) * B00 * IX(i, j > 0 ? j - 1 : 0, k0, 0);
+                    } else if (j > 0) {
+                        const int j0 = j - 1;
+                        v = CB * IX(i, j0, 0, 0);
+                        if (i > 0) v += F(i) * B10 * IX(i > 0 ? i - 1 : 0, j0, 0, 0);
+                        if (j0 > 0) v += F(j0) * B10 * IX(i, j0 > 0 ? j0 - 1 : 0, 0, 0);
+                    } else if (i > 0) {
+                        const int i0 = i - 1;
+                        v = CA * IX(i0, 0, 0, 0);
+                        if (i0 > 0) v += F(i0) * B10 * IX(i0 > 0 ? i0 - 1 : 0, 0, 0, 0);
+                    } else {
+                        v = I0;
+                    }
+                    IX(i, j, k, l) = v;
+                }
+#pragma unroll
+    for (int i = 0; i <= LA; ++i)
+#pragma unroll
+        for (int j = 0; j <= LB; ++j)
+#pragma unroll
+            for (int k = 0; k <= LC; ++k)
+#pragma unroll
+                for (int l = 0; l <= LD; ++l) {
+                    const int e = ((i * NB1 + j) * NC1 + k) * ND1 + l;
+                    const F v = I[e];
+                    const F im = i ? F(i) * IX(i ? i - 1 : 0, j, k, l) : F(0);
+                    const F jm = j ? F(j) * IX(i, j ? j - 1 : 0, k, l) : F(0);
+                    const F km = k ? F(k) * IX(i, j, k ? k - 1 : 0, l) : F(0);
+                    const F lm = l ? F(l) * IX(i, j, k, l ? l - 1 : 0) : F(0);
+                    out[e] = v;
+                    out[NBASE + e] = e1 * v + e2 * im + e3 * jm + e4 * (km + lm);
+                    out[2 * NBASE + e] = f1 * v + f2 * km + f3 * lm + f4 * (im + jm);
+                    out[3 * NBASE + e] = g1 * v + g2 * km + g3 * lm + g4 * (im + jm);
+                }
+#undef IX
+}
+
+template <int LA, int LB, int LC, int LD, bool LR, typename F = double>
 struct DerivClass {
     static constexpr int L = LA + LB + LC + LD;
     static constexpr int NR = nroots_deriv(L);
@@ -89,7 +192,8 @@ struct DerivClass {
     static constexpr int N = NA * NB * NC * ND;
     static constexpr int GSTRIDE = NSET * N + 1;  // odd stride: teams start in different banks
     static constexpr int LDS_G_BYTES = 40 * 1024;
-    static constexpr int TPB_LDS = LDS_G_BYTES / (GSTRIDE * 8) > 0 ? LDS_G_BYTES / (GSTRIDE * 8) : 1;
+    static constexpr int GB = (int)sizeof(F);
+    static constexpr int TPB_LDS = LDS_G_BYTES / (GSTRIDE * GB) > 0 ? LDS_G_BYTES / (GSTRIDE * GB) : 1;
     static constexpr int TPB = TPW * 4 < TPB_LDS ? TPW * 4 : TPB_LDS;
     static constexpr int WAVES = (TPB + TPW - 1) / TPW;
     static constexpr int BLOCK = WAVES * kWave;
@@ -114,22 +218,25 @@ __device__ __forceinline__ void gamma_sym(const DerivArgs &a, int mu, int nu, in
     gl = deg * ((a.terms & 4) ? -a.beta * K : 0.0);
 }
 
-template <int LA, int LB, int LC, int LD, bool LR>
-__global__ void __launch_bounds__((DerivClass<LA, LB, LC, LD, LR>::BLOCK))
+// F: type of the 2D integrals, derivative products and per-primitive partial sums
+// (double, or float for the mixed-precision route); roots, weights, prefactors and
+// the running sums are FP64 in both.
+template <int LA, int LB, int LC, int LD, bool LR, typename F>
+__global__ void __launch_bounds__((DerivClass<LA, LB, LC, LD, LR, F>::BLOCK))
 k_deriv(const DerivArgs a)
 {
-    using K = DerivClass<LA, LB, LC, LD, LR>;
+    using K = DerivClass<LA, LB, LC, LD, LR, F>;
     constexpr int NR = K::NR, TEAM = K::TEAM, TPW = K::TPW, TPB = K::TPB;
     constexpr int NA = K::NA, NB = K::NB, NC = K::NC, ND = K::ND, N = K::N;
     extern __shared__ double s_atoms[];
-    __shared__ double s_gam[TPB * K::GSTRIDE];
+    __shared__ F s_gam[TPB * K::GSTRIDE];
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int tw = lane / TEAM, r = lane % TEAM;
     const int team = wave * TPW + tw;
     const bool lane_ok = (tw < TPW) && (team < TPB);
     const int set = r / NR, ir = r % NR;
-    double *myG = s_gam + (lane_ok ? team : 0) * K::GSTRIDE;
+    F *myG = s_gam + (lane_ok ? team : 0) * K::GSTRIDE;
 
     if (a.lds_atoms) {
         for (int i = tid; i < 3 * a.n_atoms; i += blockDim.x) s_atoms[i] = 0.0;
@@ -141,20 +248,21 @@ k_deriv(const DerivArgs a)
         const long long t = base + team;
         const bool valid = lane_ok && t < a.ntasks;
         int bra = 0, ket = 0, sa = 0, sb = 0, sc = 0, sd = 0;
+        const DerivArgs &M = (a.batch && valid) ? a.batch[a.task_mol[t]] : a;
         if (valid) {
             const int2 tk = a.tasks[t];
             bra = tk.x;
             ket = tk.y;
-            sa = a.pair_sa[bra]; sb = a.pair_sb[bra];
-            sc = a.pair_sa[ket]; sd = a.pair_sb[ket];
+            sa = M.pair_sa[bra]; sb = M.pair_sb[bra];
+            sc = M.pair_sa[ket]; sd = M.pair_sb[ket];
             const double deg = (sa != sb ? 2.0 : 1.0) * (sc != sd ? 2.0 : 1.0) * (bra != ket ? 2.0 : 1.0);
-            const int oa = a.shell_ao[sa], ob = a.shell_ao[sb], oc = a.shell_ao[sc], od = a.shell_ao[sd];
+            const int oa = M.shell_ao[sa], ob = M.shell_ao[sb], oc = M.shell_ao[sc], od = M.shell_ao[sd];
             for (int c = r; c < N; c += TEAM) {
                 const int id = c % ND, ic = (c / ND) % NC, ib = (c / (ND * NC)) % NB, ia = c / (ND * NC * NB);
                 double gf, gl;
-                gamma_sym(a, oa + ia, ob + ib, oc + ic, od + id, deg, gf, gl);
-                myG[c] = gf;
-                if constexpr (LR) myG[N + c] = gl;
+                gamma_sym(M, oa + ia, ob + ib, oc + ic, od + id, deg, gf, gl);
+                myG[c] = F(gf);
+                if constexpr (LR) myG[N + c] = F(gl);
             }
         }
         wave_sync();
@@ -163,25 +271,25 @@ k_deriv(const DerivArgs a)
         for (int k = 0; k < 9; ++k) acc[k] = 0.0;
         int atA = 0, atB = 0, atC = 0, atD = 0;
         if (valid) {
-            atA = a.shell_atom[sa]; atB = a.shell_atom[sb]; atC = a.shell_atom[sc]; atD = a.shell_atom[sd];
+            atA = M.shell_atom[sa]; atB = M.shell_atom[sb]; atC = M.shell_atom[sc]; atD = M.shell_atom[sd];
             double A[3], AB[3], Cc[3], CD[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                A[d] = a.coords[3 * atA + d];
-                AB[d] = A[d] - a.coords[3 * atB + d];
-                Cc[d] = a.coords[3 * atC + d];
-                CD[d] = Cc[d] - a.coords[3 * atD + d];
+                A[d] = M.coords[3 * atA + d];
+                AB[d] = A[d] - M.coords[3 * atB + d];
+                Cc[d] = M.coords[3 * atC + d];
+                CD[d] = Cc[d] - M.coords[3 * atD + d];
             }
-            const int pb0 = a.pair_ppoff[bra], nbp = a.pair_npp[bra];
-            const int pk0 = a.pair_ppoff[ket], nkp = a.pair_npp[ket];
-            const double *gam = myG + set * N;
+            const int pb0 = M.pair_ppoff[bra], nbp = M.pair_npp[bra];
+            const int pk0 = M.pair_ppoff[ket], nkp = M.pair_npp[ket];
+            const F *gam = myG + set * N;
             for (int ib = 0; ib < nbp; ++ib) {
-                const double p = a.pp_p[pb0 + ib], cab = a.pp_c[pb0 + ib], zb2 = 2.0 * a.pp_zb[pb0 + ib];
-                const double P[3] = {a.pp_Px[pb0 + ib], a.pp_Py[pb0 + ib], a.pp_Pz[pb0 + ib]};
+                const double p = M.pp_p[pb0 + ib], cab = M.pp_c[pb0 + ib], zb2 = 2.0 * M.pp_zb[pb0 + ib];
+                const double P[3] = {M.pp_Px[pb0 + ib], M.pp_Py[pb0 + ib], M.pp_Pz[pb0 + ib]};
                 for (int ik = 0; ik < nkp; ++ik) {
-                    const double q = a.pp_p[pk0 + ik], ccd = a.pp_c[pk0 + ik];
-                    const double zc2 = 2.0 * a.pp_za[pk0 + ik], zd2 = 2.0 * a.pp_zb[pk0 + ik];
-                    const double Q[3] = {a.pp_Px[pk0 + ik], a.pp_Py[pk0 + ik], a.pp_Pz[pk0 + ik]};
+                    const double q = M.pp_p[pk0 + ik], ccd = M.pp_c[pk0 + ik];
+                    const double zc2 = 2.0 * M.pp_za[pk0 + ik], zd2 = 2.0 * M.pp_zb[pk0 + ik];
+                    const double Q[3] = {M.pp_Px[pk0 + ik], M.pp_Py[pk0 + ik], M.pp_Pz[pk0 + ik]};
                     const double ipq = 1.0 / (p + q);
                     const double rho = p * q * ipq;
                     double PQ[3], pq2 = 0.0;
@@ -207,39 +315,87 @@ k_deriv(const DerivArgs a)
                     const double B10 = 0.5 / p * (1.0 - q * ipq * u);
                     const double B01 = 0.5 / q * (1.0 - p * ipq * u);
                     const double cq = q * ipq * u, cp = p * ipq * u;
-                    Rys2D<LA + LB + 1, LC + LD + 1, LA, LB + 1, LD + 1> g[3];
+                    F pacc[9];
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const double PA = P[d] - A[d], QC = Q[d] - Cc[d];
-                        g[d].build(d == 2 ? pref : 1.0, PA - cq * PQ[d], QC + cp * PQ[d], B10, B01, B00, AB[d], CD[d]);
+                    for (int k = 0; k < 9; ++k) pacc[k] = F(0);
+                    if constexpr (sizeof(F) == sizeof(double)) {
+                        Rys2D<LA + LB + 1, LC + LD + 1, LA, LB + 1, LD + 1, F> g[3];
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const double PA = P[d] - A[d], QC = Q[d] - Cc[d];
+                            g[d].build(F(d == 2 ? pref : 1.0), F(PA - cq * PQ[d]), F(QC + cp * PQ[d]), F(B10), F(B01),
+                                       F(B00), F(AB[d]), F(CD[d]));
+                        }
+                        const F fzb2 = F(zb2), fzc2 = F(zc2), fzd2 = F(zd2);
+#pragma unroll
+                        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                            for (int ib2 = 0; ib2 < NB; ++ib2)
+#pragma unroll
+                                for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                                    for (int id = 0; id < ND; ++id) {
+                                        const int c = ((ia * NB + ib2) * NC + ic) * ND + id;
+                                        const F gm = gam[c];
+                                        F v[3], dB[3], dC[3], dD[3];
+#pragma unroll
+                                        for (int d = 0; d < 3; ++d) {
+                                            const int i = kCart.v[LA][ia][d], j = kCart.v[LB][ib2][d];
+                                            const int k = kCart.v[LC][ic][d], l = kCart.v[LD][id][d];
+                                            const auto &X = g[d].X;
+                                            v[d] = X[i][j][k][l];
+                                            dB[d] = fzb2 * X[i][j + 1][k][l] - (j ? F(j) * X[i][j ? j - 1 : 0][k][l] : F(0));
+                                            dC[d] = fzc2 * X[i][j][k + 1][l] - (k ? F(k) * X[i][j][k ? k - 1 : 0][l] : F(0));
+                                            dD[d] = fzd2 * X[i][j][k][l + 1] - (l ? F(l) * X[i][j][k][l ? l - 1 : 0] : F(0));
+                                        }
+                                        const F gz = gm * v[2];
+                                        const F tyz = gz * v[1], txz = gz * v[0], txy = gm * v[0] * v[1];
+                                        pacc[0] += tyz * dB[0]; pacc[1] += txz * dB[1]; pacc[2] += txy * dB[2];
+                                        pacc[3] += tyz * dC[0]; pacc[4] += txz * dC[1]; pacc[5] += txy * dC[2];
+                                        pacc[6] += tyz * dD[0]; pacc[7] += txz * dD[1]; pacc[8] += txy * dD[2];
+                                    }
+                    } else {
+                        constexpr int NBASE = (LA + 1) * (LB + 1) * (LC + 1) * (LD + 1);
+                        const double za = M.pp_za[pb0 + ib];
+                        const DirectCoef dc = direct_coef(za, 0.5 * zb2, 0.5 * zc2, 0.5 * zd2, p, q, u, ipq, B10, B01, B00);
+                        F T[3][4 * NBASE];
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const double CA = (P[d] - A[d]) - cq * PQ[d], CB = CA + AB[d];
+                            const double CCx = (Q[d] - Cc[d]) + cp * PQ[d], CDx = CCx + CD[d];
+                            direct_tables<LA, LB, LC, LD, F>(T[d], F(d == 2 ? pref : 1.0), F(CA), F(CB), F(CCx), F(CDx),
+                                                             F(B10), F(B01), F(B00), F(zb2 * CB), F(dc.e2), F(dc.e3),
+                                                             F(dc.e4), F(zc2 * CCx), F(dc.f2), F(dc.f3), F(dc.f4),
+                                                             F(zd2 * CDx), F(dc.g2), F(dc.g3), F(dc.g4));
+                        }
+#pragma unroll
+                        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                            for (int ib2 = 0; ib2 < NB; ++ib2)
+#pragma unroll
+                                for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                                    for (int id = 0; id < ND; ++id) {
+                                        const int c = ((ia * NB + ib2) * NC + ic) * ND + id;
+                                        const F gm = gam[c];
+                                        int e[3];
+#pragma unroll
+                                        for (int d = 0; d < 3; ++d)
+                                            e[d] = ((kCart.v[LA][ia][d] * (LB + 1) + kCart.v[LB][ib2][d]) * (LC + 1) +
+                                                    kCart.v[LC][ic][d]) * (LD + 1) + kCart.v[LD][id][d];
+                                        const F vx = T[0][e[0]], vy = T[1][e[1]], vz = T[2][e[2]];
+                                        const F gz = gm * vz;
+                                        const F tyz = gz * vy, txz = gz * vx, txy = gm * vx * vy;
+                                        pacc[0] += tyz * T[0][NBASE + e[0]]; pacc[3] += tyz * T[0][2 * NBASE + e[0]];
+                                        pacc[6] += tyz * T[0][3 * NBASE + e[0]];
+                                        pacc[1] += txz * T[1][NBASE + e[1]]; pacc[4] += txz * T[1][2 * NBASE + e[1]];
+                                        pacc[7] += txz * T[1][3 * NBASE + e[1]];
+                                        pacc[2] += txy * T[2][NBASE + e[2]]; pacc[5] += txy * T[2][2 * NBASE + e[2]];
+                                        pacc[8] += txy * T[2][3 * NBASE + e[2]];
+                                    }
                     }
 #pragma unroll
-                    for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                        for (int ib2 = 0; ib2 < NB; ++ib2)
-#pragma unroll
-                            for (int ic = 0; ic < NC; ++ic)
-#pragma unroll
-                                for (int id = 0; id < ND; ++id) {
-                                    const int c = ((ia * NB + ib2) * NC + ic) * ND + id;
-                                    const double gm = gam[c];
-                                    double v[3], dB[3], dC[3], dD[3];
-#pragma unroll
-                                    for (int d = 0; d < 3; ++d) {
-                                        const int i = kCart.v[LA][ia][d], j = kCart.v[LB][ib2][d];
-                                        const int k = kCart.v[LC][ic][d], l = kCart.v[LD][id][d];
-                                        const auto &X = g[d].X;
-                                        v[d] = X[i][j][k][l];
-                                        dB[d] = zb2 * X[i][j + 1][k][l] - (j ? j * X[i][j ? j - 1 : 0][k][l] : 0.0);
-                                        dC[d] = zc2 * X[i][j][k + 1][l] - (k ? k * X[i][j][k ? k - 1 : 0][l] : 0.0);
-                                        dD[d] = zd2 * X[i][j][k][l + 1] - (l ? l * X[i][j][k][l ? l - 1 : 0] : 0.0);
-                                    }
-                                    const double gz = gm * v[2];
-                                    const double tyz = gz * v[1], txz = gz * v[0], txy = gm * v[0] * v[1];
-                                    acc[0] += tyz * dB[0]; acc[1] += txz * dB[1]; acc[2] += txy * dB[2];
-                                    acc[3] += tyz * dC[0]; acc[4] += txz * dC[1]; acc[5] += txy * dC[2];
-                                    acc[6] += tyz * dD[0]; acc[7] += txz * dD[1]; acc[8] += txy * dD[2];
-                                }
+                    for (int k = 0; k < 9; ++k) acc[k] += double(pacc[k]);
                 }
             }
         }
@@ -262,7 +418,7 @@ k_deriv(const DerivArgs a)
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         if (a.lds_atoms) atomicAdd(&s_atoms[3 * at[X] + d], out[3 * X + d]);
-                        else atomic_add_global(&a.grad[3 * at[X] + d], out[3 * X + d]);
+                        else atomic_add_global(&M.grad[3 * at[X] + d], out[3 * X + d]);
                     }
             }
         }

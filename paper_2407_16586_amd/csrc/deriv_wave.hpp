@@ -17,7 +17,7 @@
 
 namespace tdg {
 
-template <int LA, int LB, int LC, int LD, bool LR>
+template <int LA, int LB, int LC, int LD, bool LR, typename F = double>
 struct WaveClass {
     static constexpr int L = LA + LB + LC + LD;
     static constexpr int NR = nroots_deriv(L);
@@ -27,12 +27,13 @@ struct WaveClass {
     static constexpr int N = NA * NB * NC * ND;
     static constexpr int NBASE = (LA + 1) * (LB + 1) * (LC + 1) * (LD + 1);
     static constexpr int TAB = 12 * NBASE;               // doubles per slot (3 dirs x 4 kinds)
-    static constexpr int CH_LDS = (14 * 1024) / (TAB * 8) > 0 ? (14 * 1024) / (TAB * 8) : 1;
+    static constexpr int FB = (int)sizeof(F);
+    static constexpr int CH_LDS = (14 * 1024) / (TAB * FB) > 0 ? (14 * 1024) / (TAB * FB) : 1;
     static constexpr int CH0 = CH_LDS < NSLOT ? CH_LDS : NSLOT;
     static constexpr int CH = CH0 * 3 <= kWave ? CH0 : kWave / 3;
     static constexpr int NCHUNK = (NSLOT + CH - 1) / CH;
-    static constexpr int WAVE_LDS = CH * TAB;            // doubles per wave
-    static constexpr int WAVES = WAVE_LDS * 8 * 4 <= 64 * 1024 ? 4 : 2;
+    static constexpr int WAVE_LDS = CH * TAB;            // elements per wave
+    static constexpr int WAVES = WAVE_LDS * FB * 4 <= 64 * 1024 ? 4 : 2;
     static constexpr int BLOCK = WAVES * kWave;
     static constexpr int CPL = (N + kWave - 1) / kWave;  // components per lane
 };
@@ -45,31 +46,30 @@ __host__ __device__ constexpr int binom(int n, int k)
 }
 
 // Build the derivative-ready tables of one root and one direction into LDS.
-template <int LA, int LB, int LC, int LD>
-__device__ __forceinline__ void wave_table(double *out /* [4][NBASE] */, double I0, double C00, double D00, double B10,
-                                           double B01, double B00, double AB, double CD, double zb2, double zc2,
-                                           double zd2)
+template <int LA, int LB, int LC, int LD, typename F>
+__device__ __forceinline__ void wave_table(F *out /* [4][NBASE] */, F I0, F C00, F D00, F B10, F B01, F B00, F AB,
+                                           F CD, F zb2, F zc2, F zd2)
 {
     constexpr int NM = LA + LB + 1, MM = LC + LD + 1;
     constexpr int NBASE = (LA + 1) * (LB + 1) * (LC + 1) * (LD + 1);
-    double V[NM + 1][MM + 1];
+    F V[NM + 1][MM + 1];
     V[0][0] = I0;
     if constexpr (NM >= 1) V[1][0] = C00 * I0;
 #pragma unroll
-    for (int n = 1; n < NM; ++n) V[n + 1][0] = C00 * V[n][0] + (n * B10) * V[n - 1][0];
+    for (int n = 1; n < NM; ++n) V[n + 1][0] = C00 * V[n][0] + (F(n) * B10) * V[n - 1][0];
 #pragma unroll
     for (int m = 0; m < MM; ++m)
 #pragma unroll
         for (int n = 0; n <= NM; ++n) {
-            double v = D00 * V[n][m];
-            if (m > 0) v += (m * B01) * V[n][m > 0 ? m - 1 : 0];
-            if (n > 0) v += (n * B00) * V[n > 0 ? n - 1 : 0][m];
+            F v = D00 * V[n][m];
+            if (m > 0) v += (F(m) * B01) * V[n][m > 0 ? m - 1 : 0];
+            if (n > 0) v += (F(n) * B00) * V[n > 0 ? n - 1 : 0][m];
             V[n][m + 1] = v;
         }
     // powers of AB and CD for the binomial transfers
-    double abp[LB + 2], cdp[LD + 2];
-    abp[0] = 1.0;
-    cdp[0] = 1.0;
+    F abp[LB + 2], cdp[LD + 2];
+    abp[0] = F(1);
+    cdp[0] = F(1);
 #pragma unroll
     for (int t = 1; t < LB + 2; ++t) abp[t] = abp[t - 1] * AB;
 #pragma unroll
@@ -77,15 +77,15 @@ __device__ __forceinline__ void wave_table(double *out /* [4][NBASE] */, double 
 #pragma unroll
     for (int i = 0; i <= LA; ++i) {
         // W[j][m] = (i, j | m) = sum_t C(j,t) AB^(j-t) V[i+t][m]
-        double X[LB + 2][LC + 2][LD + 2];
+        F X[LB + 2][LC + 2][LD + 2];
 #pragma unroll
         for (int j = 0; j <= LB + 1; ++j) {
-            double W[MM + 1];
+            F W[MM + 1];
 #pragma unroll
             for (int m = 0; m <= MM; ++m) {
-                double s = 0.0;
+                F s = F(0);
 #pragma unroll
-                for (int t = 0; t <= j; ++t) s += (binom(j, t) * abp[j - t]) * V[i + t][m];
+                for (int t = 0; t <= j; ++t) s += (F(binom(j, t)) * abp[j - t]) * V[i + t][m];
                 W[m] = s;
             }
             // X[k][l] = (i, j | k, l) = sum_s C(l,s) CD^(l-s) W[k+s], k + l <= MM
@@ -94,9 +94,9 @@ __device__ __forceinline__ void wave_table(double *out /* [4][NBASE] */, double 
 #pragma unroll
                 for (int l = 0; l <= LD + 1; ++l) {
                     if (k + l > MM) continue;
-                    double s = 0.0;
+                    F s = F(0);
 #pragma unroll
-                    for (int u = 0; u <= l; ++u) s += (binom(l, u) * cdp[l - u]) * W[k + u];
+                    for (int u = 0; u <= l; ++u) s += (F(binom(l, u)) * cdp[l - u]) * W[k + u];
                     X[j][k][l] = s;
                 }
         }
@@ -108,25 +108,25 @@ __device__ __forceinline__ void wave_table(double *out /* [4][NBASE] */, double 
                 for (int l = 0; l <= LD; ++l) {
                     const int e = ((i * (LB + 1) + j) * (LC + 1) + k) * (LD + 1) + l;
                     out[e] = X[j][k][l];
-                    out[NBASE + e] = zb2 * X[j + 1][k][l] - (j ? j * X[j ? j - 1 : 0][k][l] : 0.0);
-                    out[2 * NBASE + e] = zc2 * X[j][k + 1][l] - (k ? k * X[j][k ? k - 1 : 0][l] : 0.0);
-                    out[3 * NBASE + e] = zd2 * X[j][k][l + 1] - (l ? l * X[j][k][l ? l - 1 : 0] : 0.0);
+                    out[NBASE + e] = zb2 * X[j + 1][k][l] - (j ? F(j) * X[j ? j - 1 : 0][k][l] : F(0));
+                    out[2 * NBASE + e] = zc2 * X[j][k + 1][l] - (k ? F(k) * X[j][k ? k - 1 : 0][l] : F(0));
+                    out[3 * NBASE + e] = zd2 * X[j][k][l + 1] - (l ? F(l) * X[j][k][l ? l - 1 : 0] : F(0));
                 }
     }
 }
 
-template <int LA, int LB, int LC, int LD, bool LR>
-__global__ void __launch_bounds__((WaveClass<LA, LB, LC, LD, LR>::BLOCK))
+template <int LA, int LB, int LC, int LD, bool LR, typename F>
+__global__ void __launch_bounds__((WaveClass<LA, LB, LC, LD, LR, F>::BLOCK))
 k_deriv_wave(const DerivArgs a)
 {
-    using K = WaveClass<LA, LB, LC, LD, LR>;
+    using K = WaveClass<LA, LB, LC, LD, LR, F>;
     constexpr int NR = K::NR, NSLOT = K::NSLOT, CH = K::CH, NCHUNK = K::NCHUNK, CPL = K::CPL;
     constexpr int NB = K::NB, NC = K::NC, ND = K::ND, N = K::N, NBASE = K::NBASE, TAB = K::TAB;
     extern __shared__ double s_atoms[];
-    __shared__ double s_tab[K::WAVES * K::WAVE_LDS];
+    __shared__ F s_tab[K::WAVES * K::WAVE_LDS];
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    double *tab = s_tab + wave * K::WAVE_LDS;
+    F *tab = s_tab + wave * K::WAVE_LDS;
     if (a.lds_atoms) {
         for (int i = tid; i < 3 * a.n_atoms; i += blockDim.x) s_atoms[i] = 0.0;
         __syncthreads();
@@ -149,46 +149,50 @@ k_deriv_wave(const DerivArgs a)
     const double om2 = a.omega * a.omega;
     const long long wstride = (long long)gridDim.x * K::WAVES;
     for (long long t = (long long)blockIdx.x * K::WAVES + wave; t < a.ntasks; t += wstride) {
+        const DerivArgs &M = a.batch ? a.batch[a.task_mol[t]] : a;
         const int2 tk = a.tasks[t];
         const int bra = tk.x, ket = tk.y;
-        const int sa = a.pair_sa[bra], sb = a.pair_sb[bra], sc = a.pair_sa[ket], sd = a.pair_sb[ket];
+        const int sa = M.pair_sa[bra], sb = M.pair_sb[bra], sc = M.pair_sa[ket], sd = M.pair_sb[ket];
         const double deg = (sa != sb ? 2.0 : 1.0) * (sc != sd ? 2.0 : 1.0) * (bra != ket ? 2.0 : 1.0);
-        const int oa = a.shell_ao[sa], ob = a.shell_ao[sb], oc = a.shell_ao[sc], od = a.shell_ao[sd];
-        double gam[CPL][2];
+        const int oa = M.shell_ao[sa], ob = M.shell_ao[sb], oc = M.shell_ao[sc], od = M.shell_ao[sd];
+        F gam[CPL][2];
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
-            gam[q][0] = gam[q][1] = 0.0;
+            gam[q][0] = gam[q][1] = F(0);
             if (cok[q]) {
                 const int c = lane + q * kWave;
                 const int id = c % ND, ic = (c / ND) % NC, ib = (c / (ND * NC)) % NB, ia = c / (ND * NC * NB);
-                gamma_sym(a, oa + ia, ob + ib, oc + ic, od + id, deg, gam[q][0], gam[q][1]);
+                double gf, gl;
+                gamma_sym(M, oa + ia, ob + ib, oc + ic, od + id, deg, gf, gl);
+                gam[q][0] = F(gf);
+                gam[q][1] = F(gl);
             }
         }
-        const int atA = a.shell_atom[sa], atB = a.shell_atom[sb], atC = a.shell_atom[sc], atD = a.shell_atom[sd];
+        const int atA = M.shell_atom[sa], atB = M.shell_atom[sb], atC = M.shell_atom[sc], atD = M.shell_atom[sd];
         // stage-1 lane role
         const int s1 = lane / 3, d1 = lane % 3;
         double Ad = 0.0, ABd = 0.0, Cd = 0.0, CDd = 0.0;
         if (s1 < CH) {
-            Ad = a.coords[3 * atA + d1];
-            ABd = Ad - a.coords[3 * atB + d1];
-            Cd = a.coords[3 * atC + d1];
-            CDd = Cd - a.coords[3 * atD + d1];
+            Ad = M.coords[3 * atA + d1];
+            ABd = Ad - M.coords[3 * atB + d1];
+            Cd = M.coords[3 * atC + d1];
+            CDd = Cd - M.coords[3 * atD + d1];
         }
         double acc[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) acc[k] = 0.0;
-        const int pb0 = a.pair_ppoff[bra], nbp = a.pair_npp[bra];
-        const int pk0 = a.pair_ppoff[ket], nkp = a.pair_npp[ket];
+        const int pb0 = M.pair_ppoff[bra], nbp = M.pair_npp[bra];
+        const int pk0 = M.pair_ppoff[ket], nkp = M.pair_npp[ket];
         for (int ib = 0; ib < nbp; ++ib) {
             for (int ik = 0; ik < nkp; ++ik) {
                 for (int ch = 0; ch < NCHUNK; ++ch) {
                     const int slot = ch * CH + s1;
                     if (s1 < CH && slot < NSLOT) {
-                        const double p = a.pp_p[pb0 + ib], cab = a.pp_c[pb0 + ib], zb2 = 2.0 * a.pp_zb[pb0 + ib];
-                        const double q = a.pp_p[pk0 + ik], ccd = a.pp_c[pk0 + ik];
-                        const double zc2 = 2.0 * a.pp_za[pk0 + ik], zd2 = 2.0 * a.pp_zb[pk0 + ik];
-                        const double P[3] = {a.pp_Px[pb0 + ib], a.pp_Py[pb0 + ib], a.pp_Pz[pb0 + ib]};
-                        const double Q[3] = {a.pp_Px[pk0 + ik], a.pp_Py[pk0 + ik], a.pp_Pz[pk0 + ik]};
+                        const double p = M.pp_p[pb0 + ib], cab = M.pp_c[pb0 + ib], zb2 = 2.0 * M.pp_zb[pb0 + ib];
+                        const double q = M.pp_p[pk0 + ik], ccd = M.pp_c[pk0 + ik];
+                        const double zc2 = 2.0 * M.pp_za[pk0 + ik], zd2 = 2.0 * M.pp_zb[pk0 + ik];
+                        const double P[3] = {M.pp_Px[pb0 + ib], M.pp_Py[pb0 + ib], M.pp_Pz[pb0 + ib]};
+                        const double Q[3] = {M.pp_Px[pk0 + ik], M.pp_Py[pk0 + ik], M.pp_Pz[pk0 + ik]};
                         const double ipq = 1.0 / (p + q), rho = p * q * ipq;
                         const double PQ0 = P[0] - Q[0], PQ1 = P[1] - Q[1], PQ2 = P[2] - Q[2];
                         const double pq2 = PQ0 * PQ0 + PQ1 * PQ1 + PQ2 * PQ2;
@@ -210,9 +214,23 @@ k_deriv_wave(const DerivArgs a)
                         const double B01 = 0.5 / q * (1.0 - p * ipq * u);
                         const double PQd = d1 == 0 ? PQ0 : (d1 == 1 ? PQ1 : PQ2);
                         const double Pd = P[d1 == 0 ? 0 : (d1 == 1 ? 1 : 2)], Qd = Q[d1 == 0 ? 0 : (d1 == 1 ? 1 : 2)];
-                        wave_table<LA, LB, LC, LD>(tab + s1 * TAB + d1 * 4 * NBASE, d1 == 2 ? pref : 1.0,
-                                                   (Pd - Ad) - q * ipq * u * PQd, (Qd - Cd) + p * ipq * u * PQd, B10,
-                                                   B01, B00, ABd, CDd, zb2, zc2, zd2);
+                        if constexpr (sizeof(F) == sizeof(double)) {
+                            wave_table<LA, LB, LC, LD, F>(tab + s1 * TAB + d1 * 4 * NBASE, F(d1 == 2 ? pref : 1.0),
+                                                          F((Pd - Ad) - q * ipq * u * PQd),
+                                                          F((Qd - Cd) + p * ipq * u * PQd), F(B10), F(B01), F(B00), F(ABd),
+                                                          F(CDd), F(zb2), F(zc2), F(zd2));
+                        } else {
+                            const double za = M.pp_za[pb0 + ib];
+                            const DirectCoef dc =
+                                direct_coef(za, 0.5 * zb2, 0.5 * zc2, 0.5 * zd2, p, q, u, ipq, B10, B01, B00);
+                            const double CA = (Pd - Ad) - q * ipq * u * PQd, CB = CA + ABd;
+                            const double CCx = (Qd - Cd) + p * ipq * u * PQd, CDx = CCx + CDd;
+                            F *o = tab + s1 * TAB + d1 * 4 * NBASE;
+                            direct_tables<LA, LB, LC, LD, F>(o, F(d1 == 2 ? pref : 1.0), F(CA), F(CB), F(CCx), F(CDx),
+                                                             F(B10), F(B01), F(B00), F(zb2 * CB), F(dc.e2), F(dc.e3),
+                                                             F(dc.e4), F(zc2 * CCx), F(dc.f2), F(dc.f3), F(dc.f4),
+                                                             F(zd2 * CDx), F(dc.g2), F(dc.g3), F(dc.g4));
+                        }
                     }
                     wave_sync();
 #pragma unroll
@@ -220,25 +238,30 @@ k_deriv_wave(const DerivArgs a)
                         const int slot2 = ch * CH + s;
                         if (slot2 >= NSLOT) break;
                         const int set = slot2 / NR;
-                        const double *T = tab + s * TAB;
+                        const F *T = tab + s * TAB;
+                        F pacc[9];
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) pacc[k] = F(0);
 #pragma unroll
                         for (int q = 0; q < CPL; ++q) {
                             if (!cok[q]) continue;
-                            const double gm = gam[q][LR ? set : 0];
+                            const F gm = gam[q][LR ? set : 0];
                             const int ex = eoff[q][0], ey = eoff[q][1], ez = eoff[q][2];
-                            const double vx = T[ex], vy = T[ey], vz = T[ez];
-                            const double gz = gm * vz;
-                            const double tyz = gz * vy, txz = gz * vx, txy = gm * vx * vy;
-                            acc[0] += tyz * T[ex + NBASE];
-                            acc[3] += tyz * T[ex + 2 * NBASE];
-                            acc[6] += tyz * T[ex + 3 * NBASE];
-                            acc[1] += txz * T[ey + NBASE];
-                            acc[4] += txz * T[ey + 2 * NBASE];
-                            acc[7] += txz * T[ey + 3 * NBASE];
-                            acc[2] += txy * T[ez + NBASE];
-                            acc[5] += txy * T[ez + 2 * NBASE];
-                            acc[8] += txy * T[ez + 3 * NBASE];
+                            const F vx = T[ex], vy = T[ey], vz = T[ez];
+                            const F gz = gm * vz;
+                            const F tyz = gz * vy, txz = gz * vx, txy = gm * vx * vy;
+                            pacc[0] += tyz * T[ex + NBASE];
+                            pacc[3] += tyz * T[ex + 2 * NBASE];
+                            pacc[6] += tyz * T[ex + 3 * NBASE];
+                            pacc[1] += txz * T[ey + NBASE];
+                            pacc[4] += txz * T[ey + 2 * NBASE];
+                            pacc[7] += txz * T[ey + 3 * NBASE];
+                            pacc[2] += txy * T[ez + NBASE];
+                            pacc[5] += txy * T[ez + 2 * NBASE];
+                            pacc[8] += txy * T[ez + 3 * NBASE];
                         }
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) acc[k] += double(pacc[k]);
                     }
                     wave_sync();
                 }
@@ -258,7 +281,7 @@ k_deriv_wave(const DerivArgs a)
             const int at = X == 0 ? atA : (X == 1 ? atB : (X == 2 ? atC : atD));
             if (a.task_out) atomic_add_global(&a.task_out[12 * t + lane], v);
             else if (a.lds_atoms) atomicAdd(&s_atoms[3 * at + d], v);
-            else atomic_add_global(&a.grad[3 * at + d], v);
+            else atomic_add_global(&M.grad[3 * at + d], v);
         }
     }
     if (a.lds_atoms) {

@@ -24,8 +24,9 @@
 #include <vector>
 
 #include "../../include/tdgrad.h"
+#include "class_launch.hpp"
 #include "deriv_kernel.hpp"
-#include "deriv_wave.hpp"
+#include "mlp.hpp"
 
 using namespace tdg;
 
@@ -42,6 +43,12 @@ static int fail(int code, const char *fmt, ...)
     va_end(ap);
     g_err = buf;
     return code;
+}
+
+extern "C" int tdg_set_error_(int code, const char *msg) { return fail(code, "%s", msg); }
+
+namespace tdg {
+void mlp_device_ptrs(const tdg_mlp *m, const float **w, const uint16_t **w1b, const uint16_t **w2b);
 }
 
 #define HIP_TRY(expr)                                                                              \
@@ -135,9 +142,32 @@ struct tdg_plan {
     std::vector<int> item_class_off;       // [22] offset of each class's items
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ev_cls[kNumClasses + 1] = {};
-    int variant[kNumClasses];              // kernel variant per class (0 team-per-quartet, 1 wave-per-quartet)
+    int variant[2][kNumClasses];           // kernel variant per (precision, class): 0 team, 1 wavefront
+    std::vector<double> pair_pmax;         // largest primitive exponent sum of each sorted pair
+    DevBuf<double> d_pair_pmax;
+    std::vector<double> pair_famp;         // FP32 error-amplification proxy of each sorted pair
+    DevBuf<double> d_pair_famp;
+    DevBuf<int> d_item_cnt32;              // per (class, bra pair) FP32-routed survivor counts
+    DevBuf<long long> d_item_off32;
     bool tuned = false;                    // variants measured on this plan's first call
     DevBuf<double> d_grad_tune;            // scratch gradient for the tuning launches
+    // buffers of batched calls led by this plan (the first plan of tdg_grad_jk_batch)
+    DevBuf<int2> d_btasks;
+    DevBuf<int> d_bmol;
+    DevBuf<DerivArgs> d_bargs;
+    int bvariant[2][kNumClasses];
+    bool btuned = false;
+    // learned screening (a13): estimator and thresholds (log10 of the contribution)
+    const tdg_mlp *ml = nullptr;
+    double ml_log10 = -1e30, ml_tau_hi = 0.0;
+    std::vector<double> pair_pmin;
+    DevBuf<double> d_pair_pmin;
+    DevBuf<unsigned char> d_keep;
+    DevBuf<int2> d_tasks2;
+    DevBuf<long long> d_blkcnt, d_segcnt;
+    // host-side state of the current call
+    std::vector<int> h_cnt, h_cnt32;
+    std::vector<unsigned long long> h_prim, h_cand;
 };
 
 // ======================================================================= a1
@@ -278,9 +308,16 @@ struct ScreenArgs {
     int n_shells;
     double tau;
     const unsigned long long *mx;
-    int *item_cnt;                // count pass output, per bra
+    int *item_cnt;                // count pass output, per bra (FP64-routed tasks)
     const long long *item_off;    // fill pass input (absolute task index of each bra's first task)
+    int *item_cnt32;              // mixed precision: FP32-routed counts / offsets
+    const long long *item_off32;
+    const double *pair_pmax, *pair_famp;
+    int mixed;                    // 1: route to FP32 unless bound >= tau64 or an exponent sum >= p64
+    double tau64, p64;
     int2 *tasks;
+    int *task_mol;                // batched fill: molecule index per task (null: one molecule)
+    int mol;
     unsigned long long *prim_cnt; // per class
     unsigned long long *cand_cnt; // per class
 };
@@ -302,7 +339,10 @@ __device__ __forceinline__ double quartet_bound(const ScreenArgs &s, int a, int 
     return Qab * Qcd * m;
 }
 
-// one wavefront per bra pair; FILL = false counts, true writes the tasks in order
+// one wavefront per bra pair; FILL = false counts, true writes the tasks in order.
+// In the mixed-precision mode a survivor goes to the FP32 list when its bound times
+// the two pairs' FP32 error-amplification factors is < tau64 and no primitive exponent
+// sum reaches p64; otherwise to the FP64 list.
 template <bool FILL>
 __global__ void __launch_bounds__(256) k_screen(const ScreenArgs s)
 {
@@ -315,8 +355,10 @@ __global__ void __launch_bounds__(256) k_screen(const ScreenArgs s)
     const double cut = s.tau > 0.0 ? s.tau / (Qi * mxv * mxv) : -1.0;
     const int ata = s.shell_atom[a], atb = s.shell_atom[b];
     const int Ki = s.pair_K[i];
-    long long out = FILL ? s.item_off[wid] : 0;
-    int cnt = 0;
+    const bool hot_i = s.mixed && s.pair_pmax[i] >= s.p64;
+    const double famp_i = s.mixed ? s.pair_famp[i] : 0.0;
+    long long out = FILL ? s.item_off[wid] : 0, out32 = (FILL && s.mixed) ? s.item_off32[wid] : 0;
+    int cnt = 0, cnt32 = 0;
     unsigned long long prim = 0, cand = 0;
     for (int g = s.grp0; g < s.grp1; ++g) {
         const int g0 = s.grp_start[g], g1 = s.grp_start[g + 1];
@@ -333,28 +375,36 @@ __global__ void __launch_bounds__(256) k_screen(const ScreenArgs s)
         if (hi > g0) cand += hi - g0;
         for (int j0 = g0; j0 < hi; j0 += kWave) {
             const int j = j0 + lane;
-            bool keep = false;
+            bool keep = false, to32 = false;
             if (j < hi) {
                 const int c = s.pair_sa[j], d = s.pair_sb[j];
                 const bool one_center = (s.shell_atom[c] == ata) && (s.shell_atom[d] == ata) && (atb == ata);
-                keep = !one_center && (s.tau <= 0.0 || quartet_bound(s, a, b, c, d, Qi, s.pair_Q[j]) >= s.tau);
+                if (!one_center) {
+                    const double bnd = quartet_bound(s, a, b, c, d, Qi, s.pair_Q[j]);
+                    keep = s.tau <= 0.0 || bnd >= s.tau;
+                    to32 = keep && s.mixed && !hot_i && bnd * famp_i * s.pair_famp[j] < s.tau64 &&
+                           s.pair_pmax[j] < s.p64;
+                }
                 if (keep) prim += (unsigned long long)Ki * s.pair_K[j];
             }
-            const unsigned long long mask = __ballot(keep);
+            const unsigned long long m64 = __ballot(keep && !to32), m32 = __ballot(to32);
+            const unsigned long long below = (1ull << lane) - 1ull;
             if (FILL && keep) {
-                const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-                s.tasks[out + rank] = make_int2(i, j);
+                const long long pos = to32 ? out32 + __popcll(m32 & below) : out + __popcll(m64 & below);
+                s.tasks[pos] = make_int2(i, j);
+                if (s.task_mol) s.task_mol[pos] = s.mol;
             }
-            const int nk = __popcll(mask);
-            out += nk;
-            cnt += nk;
+            out += __popcll(m64);
+            out32 += __popcll(m32);
+            cnt += __popcll(m64);
+            cnt32 += __popcll(m32);
         }
     }
     if (!FILL) {
-        // wave reduction of the primitive count
         for (int off = 32; off > 0; off >>= 1) prim += __shfl_xor(prim, off);
         if (lane == 0) {
             s.item_cnt[wid] = cnt;
+            if (s.mixed) s.item_cnt32[wid] = cnt32;
             atomicAdd(s.prim_cnt + s.cls, prim);
             atomicAdd(s.cand_cnt + s.cls, cand);
         }
@@ -368,67 +418,176 @@ __global__ void k_zero(double *p, long long n)
 }
 
 // ======================================================================= dispatch
-template <int LA, int LB, int LC, int LD, bool LR>
-static hipError_t launch_one(int variant, const DerivArgs &a, hipStream_t st, int grid_max)
+// ======================================================================= a13
+// Features of a shell quartet for the contribution estimator (10 used of 16):
+//   log10 Q_ab, log10 Q_cd, log10 of the largest density-block product (all /10),
+//   log10 of the smallest and largest primitive exponent sums of both pairs (/4),
+//   distance between the pairs' bond midpoints (/10), total angular momentum (/8),
+//   |AB| + |CD| (/10).
+struct FeatArgs {
+    const int *pair_sa, *pair_sb, *shell_atom, *shell_l;
+    const double *pair_Q, *pair_pmin, *pair_pmax, *coords;
+    const double *mP, *mD, *mR;
+    int n_shells;
+};
+
+__device__ inline void quartet_features(const FeatArgs &f, int bra, int ket, float *x)
 {
-    const size_t dyn = a.lds_atoms ? (size_t)3 * a.n_atoms * sizeof(double) : 0;
-    if (variant == 0) {
-        using K = DerivClass<LA, LB, LC, LD, LR>;
-        const long long blocks_needed = (a.ntasks + K::TPB - 1) / K::TPB;
-        const int grid = (int)std::min<long long>(blocks_needed, grid_max);
-        hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
-    } else {
-        using K = WaveClass<LA, LB, LC, LD, LR>;
-        const long long blocks_needed = (a.ntasks + K::WAVES - 1) / K::WAVES;
-        const int grid = (int)std::min<long long>(blocks_needed, grid_max);
-        hipLaunchKernelGGL((k_deriv_wave<LA, LB, LC, LD, LR>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+    const int a = f.pair_sa[bra], b = f.pair_sb[bra], c = f.pair_sa[ket], d = f.pair_sb[ket];
+    const size_t n = f.n_shells;
+#define B_(X, i, j) f.X[(size_t)(i) * n + (j)]
+    double m = B_(mD, a, b) * B_(mP, c, d);
+    m = fmax(m, B_(mP, a, b) * B_(mD, c, d));
+    m = fmax(m, B_(mR, a, b) * B_(mR, c, d));
+    m = fmax(m, B_(mD, a, c) * B_(mP, b, d));
+    m = fmax(m, B_(mD, b, d) * B_(mP, a, c));
+    m = fmax(m, B_(mD, a, d) * B_(mP, b, c));
+    m = fmax(m, B_(mD, b, c) * B_(mP, a, d));
+    m = fmax(m, B_(mR, a, c) * B_(mR, b, d));
+    m = fmax(m, B_(mR, a, d) * B_(mR, b, c));
+#undef B_
+    const double *A = f.coords + 3 * f.shell_atom[a], *B = f.coords + 3 * f.shell_atom[b];
+    const double *C = f.coords + 3 * f.shell_atom[c], *D = f.coords + 3 * f.shell_atom[d];
+    double ab2 = 0.0, cd2 = 0.0, r2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        ab2 += (A[k] - B[k]) * (A[k] - B[k]);
+        cd2 += (C[k] - D[k]) * (C[k] - D[k]);
+        const double dm = 0.5 * (A[k] + B[k]) - 0.5 * (C[k] + D[k]);
+        r2 += dm * dm;
     }
-    return hipGetLastError();
+    x[0] = (float)(log10(fmax(f.pair_Q[bra], 1e-300)) * 0.1);
+    x[1] = (float)(log10(fmax(f.pair_Q[ket], 1e-300)) * 0.1);
+    x[2] = (float)(log10(fmax(m, 1e-300)) * 0.1);
+    x[3] = (float)(log10(f.pair_pmin[bra]) * 0.25);
+    x[4] = (float)(log10(f.pair_pmin[ket]) * 0.25);
+    x[5] = (float)(log10(f.pair_pmax[bra]) * 0.25);
+    x[6] = (float)(log10(f.pair_pmax[ket]) * 0.25);
+    x[7] = (float)(sqrt(r2) * 0.1);
+    x[8] = (float)((f.shell_l[a] + f.shell_l[b] + f.shell_l[c] + f.shell_l[d]) * 0.125);
+    x[9] = (float)((sqrt(ab2) + sqrt(cd2)) * 0.1);
+    for (int k = 10; k < MLP_IN; ++k) x[k] = 0.f;
 }
 
-template <int LA, int LB, int LC, int LD>
-static hipError_t launch_lr(int variant, const DerivArgs &a, bool lr, hipStream_t st, int grid_max)
+// veto of the estimator: keep[t] = 0 when the predicted log10 contribution (target
+// scaled by 1/10) is below the threshold and the screening bound is below tau_hi
+__global__ void __launch_bounds__(256) k_ml_filter(const int2 *tasks, long long n, FeatArgs f, const float *w,
+                                                   const uint16_t *w1b, const uint16_t *w2b, float thr, double tau_hi,
+                                                   unsigned char *keep)
 {
-    return lr ? launch_one<LA, LB, LC, LD, true>(variant, a, st, grid_max)
-              : launch_one<LA, LB, LC, LD, false>(variant, a, st, grid_max);
+    __shared__ MlpShared S;
+    __shared__ MlpWave W[4];
+    mlp_load_shared(S, w1b, w2b, w);
+    __syncthreads();
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const long long stride = (long long)gridDim.x * 256;
+    for (long long base = (long long)blockIdx.x * 256 + wave * 64; base < n; base += stride) {
+        const long long t = base + lane;
+        float x[MLP_IN];
+        double bound = 0.0;
+        if (t < n) {
+            const int2 tk = tasks[t];
+            quartet_features(f, tk.x, tk.y, x);
+            bound = pow(10.0, 10.0 * ((double)x[0] + (double)x[1] + (double)x[2]));
+        } else {
+            for (int k = 0; k < MLP_IN; ++k) x[k] = 0.f;
+        }
+        const float pred = mlp_forward_wave(S, W[wave], x, lane);
+        if (t < n) keep[t] = (pred >= thr || bound >= tau_hi) ? 1 : 0;
+    }
 }
 
-static hipError_t launch_class(int c, int variant, const DerivArgs &a, bool lr, hipStream_t st, int grid_max)
+// order-preserving compaction: per-block counts, one-block exclusive scan, scatter
+__global__ void __launch_bounds__(1024) k_count_keep(const unsigned char *keep, long long n, long long *blk)
 {
-    switch (c) {
-    case 0: return launch_lr<0, 0, 0, 0>(variant, a, lr, st, grid_max);
-    case 1: return launch_lr<1, 0, 0, 0>(variant, a, lr, st, grid_max);
-    case 2: return launch_lr<1, 0, 1, 0>(variant, a, lr, st, grid_max);
-    case 3: return launch_lr<1, 1, 0, 0>(variant, a, lr, st, grid_max);
-    case 4: return launch_lr<1, 1, 1, 0>(variant, a, lr, st, grid_max);
-    case 5: return launch_lr<1, 1, 1, 1>(variant, a, lr, st, grid_max);
-    case 6: return launch_lr<2, 0, 0, 0>(variant, a, lr, st, grid_max);
-    case 7: return launch_lr<2, 0, 1, 0>(variant, a, lr, st, grid_max);
-    case 8: return launch_lr<2, 0, 1, 1>(variant, a, lr, st, grid_max);
-    case 9: return launch_lr<2, 0, 2, 0>(variant, a, lr, st, grid_max);
-    case 10: return launch_lr<2, 1, 0, 0>(variant, a, lr, st, grid_max);
-    case 11: return launch_lr<2, 1, 1, 0>(variant, a, lr, st, grid_max);
-    case 12: return launch_lr<2, 1, 1, 1>(variant, a, lr, st, grid_max);
-    case 13: return launch_lr<2, 1, 2, 0>(variant, a, lr, st, grid_max);
-    case 14: return launch_lr<2, 1, 2, 1>(variant, a, lr, st, grid_max);
-    case 15: return launch_lr<2, 2, 0, 0>(variant, a, lr, st, grid_max);
-    case 16: return launch_lr<2, 2, 1, 0>(variant, a, lr, st, grid_max);
-    case 17: return launch_lr<2, 2, 1, 1>(variant, a, lr, st, grid_max);
-    case 18: return launch_lr<2, 2, 2, 0>(variant, a, lr, st, grid_max);
-    case 19: return launch_lr<2, 2, 2, 1>(variant, a, lr, st, grid_max);
-    default: return launch_lr<2, 2, 2, 2>(variant, a, lr, st, grid_max);
+    __shared__ int s[16];
+    const long long i = (long long)blockIdx.x * 1024 + threadIdx.x;
+    const unsigned long long m = __ballot(i < n && keep[i]);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long c = 0;
+        for (int k = 0; k < 16; ++k) c += s[k];
+        blk[blockIdx.x] = c;
     }
+}
+
+__global__ void __launch_bounds__(1024) k_scan_blocks(long long *blk, long long nb, long long *total)
+{
+    __shared__ long long part[1024];
+    // each thread scans a contiguous chunk, then the chunk sums are scanned
+    const long long chunk = (nb + 1023) / 1024;
+    const long long b0 = threadIdx.x * chunk, b1 = b0 + chunk < nb ? b0 + chunk : nb;
+    long long sum = 0;
+    for (long long b = b0; b < b1; ++b) sum += blk[b];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long acc = 0;
+        for (int k = 0; k < 1024; ++k) {
+            const long long v = part[k];
+            part[k] = acc;
+            acc += v;
+        }
+        *total = acc;
+    }
+    __syncthreads();
+    long long acc = part[threadIdx.x];
+    for (long long b = b0; b < b1; ++b) {
+        const long long v = blk[b];
+        blk[b] = acc;
+        acc += v;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_scatter_keep(const int2 *in, const unsigned char *keep, long long n,
+                                                       const long long *blk, int2 *out)
+{
+    __shared__ int s[16];
+    const long long i = (long long)blockIdx.x * 1024 + threadIdx.x;
+    const bool k = i < n && keep[i];
+    const unsigned long long m = __ballot(k);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) s[w] = __popcll(m);
+    __syncthreads();
+    int before = 0;
+    for (int q = 0; q < w; ++q) before += s[q];
+    if (k) out[blk[blockIdx.x] + before + __popcll(m & ((1ull << lane) - 1ull))] = in[i];
+}
+
+// training data: features of sampled tasks and the log10 (scaled by 1/10) of the largest
+// of each task's twelve gradient contributions
+__global__ void k_collect(const int2 *tasks, long long n, long long stride, FeatArgs f, const double *contrib,
+                          float *feat, float *target, long long cap, long long out0)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = s * stride;
+    if (t >= n || out0 + s >= cap) return;
+    const int2 tk = tasks[t];
+    float x[MLP_IN];
+    quartet_features(f, tk.x, tk.y, x);
+    for (int k = 0; k < MLP_IN; ++k) feat[(out0 + s) * MLP_IN + k] = x[k];
+    double mx = 0.0;
+    for (int k = 0; k < 12; ++k) mx = fmax(mx, fabs(contrib[12 * t + k]));
+    target[out0 + s] = (float)(log10(fmax(mx, 1e-30)) * 0.1);
+}
+
+static const LaunchFn kLaunch[kNumClasses] = {
+    tdg_launch_class_0,  tdg_launch_class_1,  tdg_launch_class_2,  tdg_launch_class_3,  tdg_launch_class_4,
+    tdg_launch_class_5,  tdg_launch_class_6,  tdg_launch_class_7,  tdg_launch_class_8,  tdg_launch_class_9,
+    tdg_launch_class_10, tdg_launch_class_11, tdg_launch_class_12, tdg_launch_class_13, tdg_launch_class_14,
+    tdg_launch_class_15, tdg_launch_class_16, tdg_launch_class_17, tdg_launch_class_18, tdg_launch_class_19,
+    tdg_launch_class_20};
+
+static int class_ncomp(int c)
+{
+    int pb, pk;
+    class_pk(c, pb, pk);
+    return ncart(kPairL[pb][0]) * ncart(kPairL[pb][1]) * ncart(kPairL[pk][0]) * ncart(kPairL[pk][1]);
 }
 
 // default variant before measurement: the wave-per-quartet kernel for classes whose
 // per-lane register tables would not fit (N >= 81 Cartesian components)
-static int default_variant(int c)
-{
-    int pb, pk;
-    class_pk(c, pb, pk);
-    const int n = ncart(kPairL[pb][0]) * ncart(kPairL[pb][1]) * ncart(kPairL[pk][0]) * ncart(kPairL[pk][1]);
-    return n >= 81 ? 1 : 0;
-}
+static int default_variant(int c) { return class_ncomp(c) >= 81 ? 1 : 0; }
 
 template <int LA, int LB>
 static void launch_schwarz(tdg_plan *pl, int i0, int n, const double *ang_ab, double *Q)
@@ -604,6 +763,28 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
     pl->pc_grp_start[6] = (int)pl->grp_start.size();
     pl->grp_start.push_back(np);
     build_pp(ps, off, cnt, pp);
+    pl->pair_pmax.assign(np, 0.0);
+    pl->pair_pmin.assign(np, 1e300);
+    pl->pair_famp.assign(np, 0.0);
+    for (int i = 0; i < np; ++i) {
+        // the transfer (i, j+1) = (i+1, j) + AB (i, j) loses about |AB| zeta_b / sqrt(p) in relative
+        // precision per step when the second primitive is the tighter one (P close to B); the
+        // derivative of a Gaussian scales like sqrt(zeta)
+        const double *A = b->coords + 3 * b->shell_atom[ps[i].sa], *B = b->coords + 3 * b->shell_atom[ps[i].sb];
+        const double ab = std::sqrt((A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) +
+                                    (A[2] - B[2]) * (A[2] - B[2]));
+        const int lb = b->shell_l[ps[i].sb];
+        for (int k = off[i]; k < off[i] + cnt[i]; ++k) {
+            pl->pair_pmax[i] = std::max(pl->pair_pmax[i], pp[0][k]);
+            pl->pair_pmin[i] = std::min(pl->pair_pmin[i], pp[0][k]);
+            const double h = 1.0 + ab * pp[6][k] / std::sqrt(pp[0][k]);
+            const double f = std::pow(h, lb + 1) * std::sqrt(std::max(pp[5][k], pp[6][k]));
+            pl->pair_famp[i] = std::max(pl->pair_famp[i], f);
+        }
+    }
+    if ((rc = pl->d_pair_pmax.upload(pl->pair_pmax)) || (rc = pl->d_pair_famp.upload(pl->pair_famp)) ||
+        (rc = pl->d_pair_pmin.upload(pl->pair_pmin)))
+        return rc;
     if ((rc = pl->d_pair_sa.upload(pl->pair_sa)) || (rc = pl->d_pair_sb.upload(pl->pair_sb)) ||
         (rc = pl->d_pair_ppoff.upload(off)) || (rc = pl->d_pair_npp.upload(cnt)) || (rc = pl->d_pair_K.upload(pl->pair_K)) ||
         (rc = pl->d_pair_Q.upload(pl->pair_Q)) || (rc = pl->d_grp_start.upload(pl->grp_start)) ||
@@ -620,6 +801,7 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
     }
     const int nitems = pl->item_class_off[kNumClasses];
     if ((rc = pl->d_item_cnt.alloc(std::max(nitems, 1))) || (rc = pl->d_item_off.alloc(std::max(nitems, 1))) ||
+        (rc = pl->d_item_cnt32.alloc(std::max(nitems, 1))) || (rc = pl->d_item_off32.alloc(std::max(nitems, 1))) ||
         (rc = pl->d_prim_cnt.alloc(kNumClasses)) || (rc = pl->d_cand_cnt.alloc(kNumClasses)) || (rc = pl->d_mx.alloc(1)) ||
         (rc = pl->d_grad.alloc((size_t)3 * pl->n_atoms)) || (rc = pl->d_Pn.alloc((size_t)nbf * nbf)) ||
         (rc = pl->d_Dn.alloc((size_t)nbf * nbf)) || (rc = pl->d_Rn.alloc((size_t)nbf * nbf)) ||
@@ -629,8 +811,10 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
     HIP_TRY(hipEventCreate(&pl->ev0));
     HIP_TRY(hipEventCreate(&pl->ev1));
     for (auto &e : pl->ev_cls) HIP_TRY(hipEventCreate(&e));
-    for (int c = 0; c < kNumClasses; ++c)
-        pl->variant[c] = pl->prm.kernel_variant >= 0 ? pl->prm.kernel_variant : default_variant(c);
+    for (int pr = 0; pr < 2; ++pr)
+        for (int c = 0; c < kNumClasses; ++c)
+            pl->variant[pr][c] = pl->bvariant[pr][c] =
+                pl->prm.kernel_variant >= 0 ? pl->prm.kernel_variant : default_variant(c);
     HIP_TRY(hipDeviceSynchronize());
     return TDG_OK;
 }
@@ -667,7 +851,8 @@ int tdg_plan_create(const tdg_basis_t *basis, const tdg_params_t *params, int de
     *out = nullptr;
     int rc = check_basis(basis);
     if (rc) return rc;
-    if (params->precision != 0) return fail(TDG_EUNSUPPORTED, "precision mode %d not available", params->precision);
+    if (params->precision != 0 && params->precision != 1)
+        return fail(TDG_EUNSUPPORTED, "precision mode %d not available", params->precision);
     if ((params->terms & 4) && !(params->omega > 0.0)) return fail(TDG_EINVAL, "long-range term needs omega > 0");
     if (params->kernel_variant < -1 || params->kernel_variant > 1)
         return fail(TDG_EINVAL, "kernel_variant must be -1, 0 or 1");
@@ -703,6 +888,18 @@ int tdg_plan_destroy(tdg_plan_t *pl)
     pl->d_prim_cnt.release();
     pl->d_cand_cnt.release();
     pl->d_grad_tune.release();
+    pl->d_btasks.release();
+    pl->d_bmol.release();
+    pl->d_bargs.release();
+    pl->d_pair_pmax.release();
+    pl->d_pair_famp.release();
+    pl->d_pair_pmin.release();
+    pl->d_keep.release();
+    pl->d_tasks2.release();
+    pl->d_blkcnt.release();
+    pl->d_segcnt.release();
+    pl->d_item_cnt32.release();
+    pl->d_item_off32.release();
     for (auto &e : pl->ev_cls)
         if (e) hipEventDestroy(e);
     pl->d_mx.release();
@@ -730,16 +927,53 @@ int tdg_plan_schwarz(const tdg_plan_t *pl, double *Q)
     return TDG_OK;
 }
 
-int tdg_grad_jk(tdg_plan_t *pl, const double *P0, const double *PD, const double *R, int32_t ptr_kind,
-                void *hip_stream, double *grad, tdg_stats_t *stats)
+} // extern "C"
+
+// --------------------------------------------------------------------------
+// One or several molecules: per molecule a3 and the a4 count pass; one host
+// synchronisation for the task counts; the a4 fill pass into one task list laid
+// out per (class, precision) with the molecules concatenated; one launch per
+// (class, precision) over all molecules (a5-a10).
+
+static void screen_setup(tdg_plan *pl, ScreenArgs &s, int c)
 {
-    g_err.clear();
-    if (!pl) return fail(TDG_EINVAL, "null plan");
-    if (!P0 || !PD || !R || !grad) return fail(TDG_EINVAL, "null density or output pointer");
-    if (ptr_kind != 0 && ptr_kind != 1) return fail(TDG_EINVAL, "ptr_kind must be 0 or 1");
-    const auto t_start = std::chrono::steady_clock::now();
-    HIP_TRY(hipSetDevice(pl->device));
-    hipStream_t st = (hipStream_t)hip_stream;
+    int pb, pk;
+    class_pk(c, pb, pk);
+    s.cls = c; s.pb = pb; s.pk = pk;
+    s.bra0 = pl->pc_start[pb]; s.nbra = pl->pc_start[pb + 1] - pl->pc_start[pb];
+    s.grp0 = pl->pc_grp_start[pk]; s.grp1 = pl->pc_grp_start[pk + 1];
+    s.item_cnt = pl->d_item_cnt.p + pl->item_class_off[c];
+    s.item_off = pl->d_item_off.p + pl->item_class_off[c];
+    s.item_cnt32 = pl->d_item_cnt32.p + pl->item_class_off[c];
+    s.item_off32 = pl->d_item_off32.p + pl->item_class_off[c];
+}
+
+static ScreenArgs screen_args(tdg_plan *pl)
+{
+    ScreenArgs s{};
+    s.grp_start = pl->d_grp_start.p;
+    s.pair_sa = pl->d_pair_sa.p; s.pair_sb = pl->d_pair_sb.p; s.pair_K = pl->d_pair_K.p;
+    s.shell_atom = pl->d_shell_atom.p; s.pair_Q = pl->d_pair_Q.p;
+    s.mP = pl->d_mP.p; s.mD = pl->d_mD.p; s.mR = pl->d_mR.p;
+    s.n_shells = pl->n_shells; s.tau = pl->prm.schwarz_tol; s.mx = pl->d_mx.p;
+    s.mixed = pl->prm.precision == 1 ? 1 : 0;
+    s.tau64 = pl->prm.mixed_tau64; s.p64 = pl->prm.mixed_p64;
+    s.pair_pmax = pl->d_pair_pmax.p; s.pair_famp = pl->d_pair_famp.p;
+    s.prim_cnt = pl->d_prim_cnt.p; s.cand_cnt = pl->d_cand_cnt.p;
+    return s;
+}
+
+static bool class_active(tdg_plan *pl, int c)
+{
+    int pb, pk;
+    class_pk(c, pb, pk);
+    return pl->pc_start[pb + 1] > pl->pc_start[pb] && pl->pc_grp_start[pk + 1] > pl->pc_grp_start[pk];
+}
+
+// a3 and the count pass of a4 for one molecule (asynchronous); counts copied to host buffers
+static int prep_and_count(tdg_plan *pl, const double *P0, const double *PD, const double *R, int ptr_kind,
+                          hipStream_t st)
+{
     const int nbf = pl->n_bf, ns = pl->n_shells;
     const size_t nn = (size_t)nbf * nbf;
     int rc;
@@ -753,157 +987,397 @@ int tdg_grad_jk(tdg_plan_t *pl, const double *P0, const double *PD, const double
         dPD = pl->d_in.p + nn;
         dR = pl->d_in.p + 2 * nn;
     }
-    // a3
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (double *)pl->d_mx.p, 1);
     hipLaunchKernelGGL(k_zero, dim3((3 * pl->n_atoms + 255) / 256), dim3(256), 0, st, pl->d_grad.p,
                        (long long)3 * pl->n_atoms);
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (double *)pl->d_prim_cnt.p, (long long)kNumClasses);
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (double *)pl->d_cand_cnt.p, (long long)kNumClasses);
-    {
-        const long long nblk = (long long)ns * ns;
-        hipLaunchKernelGGL(k_density_prep, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, ns, nbf,
-                           pl->d_shell_l.p, pl->d_shell_ao.p, pl->d_ang.p, dP0, dPD, dR, pl->d_Pn.p, pl->d_Dn.p,
-                           pl->d_Rn.p, pl->d_mP.p, pl->d_mD.p, pl->d_mR.p, pl->d_mx.p);
-    }
+    const long long nblk = (long long)ns * ns;
+    hipLaunchKernelGGL(k_density_prep, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, ns, nbf,
+                       pl->d_shell_l.p, pl->d_shell_ao.p, pl->d_ang.p, dP0, dPD, dR, pl->d_Pn.p, pl->d_Dn.p,
+                       pl->d_Rn.p, pl->d_mP.p, pl->d_mD.p, pl->d_mR.p, pl->d_mx.p);
     HIP_TRY(hipGetLastError());
-    // a4: count
-    const double tau = pl->prm.schwarz_tol;
-    ScreenArgs s{};
-    s.grp_start = pl->d_grp_start.p;
-    s.pair_sa = pl->d_pair_sa.p; s.pair_sb = pl->d_pair_sb.p; s.pair_K = pl->d_pair_K.p;
-    s.shell_atom = pl->d_shell_atom.p; s.pair_Q = pl->d_pair_Q.p;
-    s.mP = pl->d_mP.p; s.mD = pl->d_mD.p; s.mR = pl->d_mR.p;
-    s.n_shells = ns; s.tau = tau; s.mx = pl->d_mx.p;
-    s.item_cnt = pl->d_item_cnt.p; s.item_off = pl->d_item_off.p; s.prim_cnt = pl->d_prim_cnt.p;
-    s.cand_cnt = pl->d_cand_cnt.p;
-    auto setup_class = [&](int c) {
-        int pb, pk;
-        class_pk(c, pb, pk);
-        s.cls = c; s.pb = pb; s.pk = pk;
-        s.bra0 = pl->pc_start[pb]; s.nbra = pl->pc_start[pb + 1] - pl->pc_start[pb];
-        s.grp0 = pl->pc_grp_start[pk]; s.grp1 = pl->pc_grp_start[pk + 1];
-        s.item_cnt = pl->d_item_cnt.p + pl->item_class_off[c];
-        s.item_off = pl->d_item_off.p + pl->item_class_off[c];
-    };
+    ScreenArgs s = screen_args(pl);
     for (int c = 0; c < kNumClasses; ++c) {
-        setup_class(c);
-        if (s.nbra == 0 || s.grp1 == s.grp0) continue;
+        if (!class_active(pl, c)) continue;
+        screen_setup(pl, s, c);
         hipLaunchKernelGGL(k_screen<false>, dim3((s.nbra + 3) / 4), dim3(256), 0, st, s);
     }
     HIP_TRY(hipGetLastError());
     const int nitems = pl->item_class_off[kNumClasses];
-    std::vector<int> cnt(nitems);
-    std::vector<unsigned long long> primc(kNumClasses), candc(kNumClasses);
-    if (nitems) HIP_TRY(hipMemcpyAsync(cnt.data(), pl->d_item_cnt.p, sizeof(int) * nitems, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(primc.data(), pl->d_prim_cnt.p, sizeof(unsigned long long) * kNumClasses,
-                           hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(candc.data(), pl->d_cand_cnt.p, sizeof(unsigned long long) * kNumClasses,
-                           hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    // empty classes were not launched: their counts are zero by construction
-    std::vector<long long> offs(nitems);
-    long long total = 0;
-    long long class_begin[kNumClasses + 1];
-    for (int c = 0; c < kNumClasses; ++c) {
-        setup_class(c);
-        class_begin[c] = total;
-        const bool launched = !(s.nbra == 0 || s.grp1 == s.grp0);
-        for (int k = pl->item_class_off[c]; k < pl->item_class_off[c + 1]; ++k) {
-            offs[k] = total;
-            if (launched) total += cnt[k];
+    pl->h_cnt.assign(nitems, 0);
+    pl->h_cnt32.assign(nitems, 0);
+    pl->h_prim.assign(kNumClasses, 0);
+    pl->h_cand.assign(kNumClasses, 0);
+    if (nitems) HIP_TRY(hipMemcpyAsync(pl->h_cnt.data(), pl->d_item_cnt.p, sizeof(int) * nitems, hipMemcpyDeviceToHost, st));
+    if (nitems && pl->prm.precision == 1)
+        HIP_TRY(hipMemcpyAsync(pl->h_cnt32.data(), pl->d_item_cnt32.p, sizeof(int) * nitems, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(pl->h_prim.data(), pl->d_prim_cnt.p, 8 * kNumClasses, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(pl->h_cand.data(), pl->d_cand_cnt.p, 8 * kNumClasses, hipMemcpyDeviceToHost, st));
+    return TDG_OK;
+}
+
+static FeatArgs feat_args(tdg_plan *pl)
+{
+    FeatArgs f{};
+    f.pair_sa = pl->d_pair_sa.p; f.pair_sb = pl->d_pair_sb.p; f.shell_atom = pl->d_shell_atom.p;
+    f.shell_l = pl->d_shell_l.p; f.pair_Q = pl->d_pair_Q.p; f.pair_pmin = pl->d_pair_pmin.p;
+    f.pair_pmax = pl->d_pair_pmax.p; f.coords = pl->d_coords.p;
+    f.mP = pl->d_mP.p; f.mD = pl->d_mD.p; f.mR = pl->d_mR.p; f.n_shells = pl->n_shells;
+    return f;
+}
+
+// a13 veto on the screened task list of one molecule: each (class, precision) segment is
+// filtered by the estimator and compacted (order kept) into the second task buffer;
+// segment ends are updated (one host synchronisation)
+static int ml_filter(tdg_plan *pl, int2 *&tasks, long long (*seg_begin)[2], long long (*seg_end)[2], hipStream_t st,
+                     long long &skipped)
+{
+    const long long total = seg_end[kNumClasses - 1][1];
+    int rc;
+    if ((rc = pl->d_keep.alloc(std::max<long long>(total, 1))) || (rc = pl->d_tasks2.alloc(std::max<long long>(total, 1))) ||
+        (rc = pl->d_segcnt.alloc(2 * kNumClasses)))
+        return rc;
+    const long long nbmax = (total + 1023) / 1024 + 2 * kNumClasses;
+    if ((rc = pl->d_blkcnt.alloc(std::max<long long>(nbmax, 1)))) return rc;
+    const float *w;
+    const uint16_t *w1b, *w2b;
+    mlp_device_ptrs(pl->ml, &w, &w1b, &w2b);
+    const FeatArgs f = feat_args(pl);
+    const float thr = (float)(pl->ml_log10 * 0.1);
+    long long boff = 0;
+    for (int c = 0; c < kNumClasses; ++c)
+        for (int pr = 0; pr < 2; ++pr) {
+            const long long b = seg_begin[c][pr], n = seg_end[c][pr] - b;
+            if (!n) {
+                hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (double *)(pl->d_segcnt.p + 2 * c + pr), 1LL);
+                continue;
+            }
+            const int grid = (int)std::min<long long>((n + 255) / 256, 8192);
+            hipLaunchKernelGGL(k_ml_filter, dim3(grid), dim3(256), 0, st, tasks + b, n, f, w, w1b, w2b, thr,
+                               pl->ml_tau_hi, pl->d_keep.p + b);
+            const long long nb = (n + 1023) / 1024;
+            hipLaunchKernelGGL(k_count_keep, dim3((unsigned)nb), dim3(1024), 0, st, pl->d_keep.p + b, n,
+                               pl->d_blkcnt.p + boff);
+            hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, pl->d_blkcnt.p + boff, nb,
+                               pl->d_segcnt.p + 2 * c + pr);
+            hipLaunchKernelGGL(k_scatter_keep, dim3((unsigned)nb), dim3(1024), 0, st, tasks + b, pl->d_keep.p + b, n,
+                               pl->d_blkcnt.p + boff, pl->d_tasks2.p + b);
+            boff += nb;
         }
-    }
-    class_begin[kNumClasses] = total;
-    if ((rc = pl->d_tasks.alloc(std::max<long long>(total, 1)))) return rc;
-    if (nitems) HIP_TRY(hipMemcpyAsync(pl->d_item_off.p, offs.data(), sizeof(long long) * nitems, hipMemcpyHostToDevice, st));
-    s.tasks = pl->d_tasks.p;
-    for (int c = 0; c < kNumClasses; ++c) {
-        setup_class(c);
-        if (s.nbra == 0 || s.grp1 == s.grp0 || class_begin[c + 1] == class_begin[c]) continue;
-        hipLaunchKernelGGL(k_screen<true>, dim3((s.nbra + 3) / 4), dim3(256), 0, st, s);
-    }
     HIP_TRY(hipGetLastError());
-    // a5-a10
-    const bool lr = (pl->prm.terms & 4) && pl->prm.beta != 0.0;
+    long long cnt[2 * kNumClasses];
+    HIP_TRY(hipMemcpyAsync(cnt, pl->d_segcnt.p, sizeof cnt, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    skipped = 0;
+    for (int c = 0; c < kNumClasses; ++c)
+        for (int pr = 0; pr < 2; ++pr) {
+            const long long n = seg_end[c][pr] - seg_begin[c][pr];
+            const long long k = n ? cnt[2 * c + pr] : 0;
+            skipped += n - k;
+            seg_end[c][pr] = seg_begin[c][pr] + k;
+        }
+    tasks = pl->d_tasks2.p;
+    return TDG_OK;
+}
+
+static DerivArgs deriv_args(tdg_plan *pl)
+{
     DerivArgs a{};
     a.coords = pl->d_coords.p; a.shell_atom = pl->d_shell_atom.p; a.shell_ao = pl->d_shell_ao.p;
     a.pair_sa = pl->d_pair_sa.p; a.pair_sb = pl->d_pair_sb.p; a.pair_ppoff = pl->d_pair_ppoff.p;
     a.pair_npp = pl->d_pair_npp.p;
     a.pp_p = pl->d_pp_p.p; a.pp_Px = pl->d_pp_Px.p; a.pp_Py = pl->d_pp_Py.p; a.pp_Pz = pl->d_pp_Pz.p;
     a.pp_c = pl->d_pp_c.p; a.pp_za = pl->d_pp_za.p; a.pp_zb = pl->d_pp_zb.p;
-    a.Pn = pl->d_Pn.p; a.Dn = pl->d_Dn.p; a.Rn = pl->d_Rn.p; a.n_bf = nbf;
+    a.Pn = pl->d_Pn.p; a.Dn = pl->d_Dn.p; a.Rn = pl->d_Rn.p; a.n_bf = pl->n_bf;
     a.omega = pl->prm.omega; a.alpha = pl->prm.alpha; a.beta = pl->prm.beta; a.terms = pl->prm.terms;
     a.grad = pl->d_grad.p; a.n_atoms = pl->n_atoms;
     a.lds_atoms = (3 * pl->n_atoms * 8 <= 24 * 1024) ? 1 : 0;
-    a.task_out = nullptr;
+    return a;
+}
+
+static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, const double *const *PD,
+                         const double *const *R, int ptr_kind, hipStream_t st, double *const *grad, tdg_stats_t *stats)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    tdg_plan *lead = pls[0];
+    HIP_TRY(hipSetDevice(lead->device));
+    int rc;
+    for (int m = 0; m < n; ++m)
+        if ((rc = prep_and_count(pls[m], P0[m], PD[m], R[m], ptr_kind, st))) return rc;
+    HIP_TRY(hipStreamSynchronize(st));
+    const bool batched = n > 1;
+    // layout: segment (class c, precision pr) = molecules in order, each [items in order]
+    long long seg_begin[kNumClasses][2], seg_end[kNumClasses][2];
+    long long total = 0;
+    std::vector<std::vector<long long>> offs(n), offs32(n);
+    for (int m = 0; m < n; ++m) {
+        offs[m].assign(pls[m]->item_class_off[kNumClasses], 0);
+        offs32[m].assign(pls[m]->item_class_off[kNumClasses], 0);
+    }
+    for (int c = 0; c < kNumClasses; ++c)
+        for (int pr = 0; pr < 2; ++pr) {
+            seg_begin[c][pr] = total;
+            for (int m = 0; m < n; ++m) {
+                tdg_plan *pl = pls[m];
+                const bool act = class_active(pl, c);
+                for (int k = pl->item_class_off[c]; k < pl->item_class_off[c + 1]; ++k) {
+                    if (pr == 0) offs[m][k] = total; else offs32[m][k] = total;
+                    if (act) total += pr == 0 ? pl->h_cnt[k] : pl->h_cnt32[k];
+                }
+            }
+            seg_end[c][pr] = total;
+        }
+    int2 *tasks;
+    int *task_mol = nullptr;
+    if (batched) {
+        if ((rc = lead->d_btasks.alloc(std::max<long long>(total, 1))) ||
+            (rc = lead->d_bmol.alloc(std::max<long long>(total, 1))))
+            return rc;
+        tasks = lead->d_btasks.p;
+        task_mol = lead->d_bmol.p;
+    } else {
+        if ((rc = lead->d_tasks.alloc(std::max<long long>(total, 1)))) return rc;
+        tasks = lead->d_tasks.p;
+    }
+    for (int m = 0; m < n; ++m) {
+        tdg_plan *pl = pls[m];
+        const int nitems = pl->item_class_off[kNumClasses];
+        if (nitems)
+            HIP_TRY(hipMemcpyAsync(pl->d_item_off.p, offs[m].data(), 8 * nitems, hipMemcpyHostToDevice, st));
+        if (nitems && pl->prm.precision == 1)
+            HIP_TRY(hipMemcpyAsync(pl->d_item_off32.p, offs32[m].data(), 8 * nitems, hipMemcpyHostToDevice, st));
+        ScreenArgs s = screen_args(pl);
+        s.tasks = tasks;
+        s.task_mol = task_mol;
+        s.mol = m;
+        for (int c = 0; c < kNumClasses; ++c) {
+            if (!class_active(pl, c)) continue;
+            screen_setup(pl, s, c);
+            hipLaunchKernelGGL(k_screen<true>, dim3((s.nbra + 3) / 4), dim3(256), 0, st, s);
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    long long ml_skipped = 0;
+    const long long screened = total;
+    if (!batched && lead->ml) {
+        if ((rc = ml_filter(lead, tasks, seg_begin, seg_end, st, ml_skipped))) return rc;
+        total = screened - ml_skipped;
+    }
+    // a5-a10
+    const bool lr = (lead->prm.terms & 4) && lead->prm.beta != 0.0;
+    DerivArgs a = deriv_args(lead);
+    if (batched) {
+        std::vector<DerivArgs> margs(n);
+        for (int m = 0; m < n; ++m) margs[m] = deriv_args(pls[m]);
+        if ((rc = lead->d_bargs.alloc(n))) return rc;
+        HIP_TRY(hipMemcpyAsync(lead->d_bargs.p, margs.data(), sizeof(DerivArgs) * n, hipMemcpyHostToDevice, st));
+        a.batch = lead->d_bargs.p;
+        a.lds_atoms = 0; // gradients of many molecules: direct FP64 atomics
+    }
+    int ncu = 256;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, lead->device) == hipSuccess) ncu = prop.multiProcessorCount;
+    }
+    const int grid_max = ncu * 8;
+    int(*variant)[kNumClasses] = batched ? lead->bvariant : lead->variant;
+    bool &tuned = batched ? lead->btuned : lead->tuned;
+    auto set_range = [&](DerivArgs &x, int c, int pr) {
+        x.tasks = tasks + seg_begin[c][pr];
+        x.task_mol = task_mol ? task_mol + seg_begin[c][pr] : nullptr;
+        x.ntasks = seg_end[c][pr] - seg_begin[c][pr];
+    };
+    if (lead->prm.autotune && lead->prm.kernel_variant < 0 && !tuned) {
+        // a12 autotuner: time the kernel variants of each (class, precision) on this call's
+        // task list (into scratch gradients) and keep the fastest for later calls.  The
+        // wavefront design is a candidate for classes with >= 27 components.
+        std::vector<DerivArgs> targs;
+        if (batched) {
+            targs.resize(n);
+            for (int m = 0; m < n; ++m) {
+                targs[m] = deriv_args(pls[m]);
+                if ((rc = pls[m]->d_grad_tune.alloc((size_t)3 * pls[m]->n_atoms))) return rc;
+                targs[m].grad = pls[m]->d_grad_tune.p;
+            }
+        }
+        DerivArgs at = a;
+        DevBuf<DerivArgs> d_targs;
+        if (batched) {
+            if ((rc = d_targs.alloc(n))) return rc;
+            HIP_TRY(hipMemcpyAsync(d_targs.p, targs.data(), sizeof(DerivArgs) * n, hipMemcpyHostToDevice, st));
+            at.batch = d_targs.p;
+        } else {
+            if ((rc = lead->d_grad_tune.alloc((size_t)3 * lead->n_atoms))) return rc;
+            at.grad = lead->d_grad_tune.p;
+        }
+        for (int pr = 0; pr < 2; ++pr)
+            for (int c = 0; c < kNumClasses; ++c) {
+                set_range(at, c, pr);
+                if (!at.ntasks || class_ncomp(c) < 27) continue;
+                float best = 1e30f;
+                for (int v = 0; v < 2; ++v) {
+                    float ms = 0.f;
+                    for (int rep = 0; rep < 2; ++rep) { // the second launch is the measured one
+                        HIP_TRY(hipEventRecord(lead->ev_cls[0], st));
+                        HIP_TRY(kLaunch[c](v, pr, at, lr, st, grid_max));
+                        HIP_TRY(hipEventRecord(lead->ev_cls[1], st));
+                        HIP_TRY(hipEventSynchronize(lead->ev_cls[1]));
+                        HIP_TRY(hipEventElapsedTime(&ms, lead->ev_cls[0], lead->ev_cls[1]));
+                    }
+                    if (ms < best) { best = ms; variant[pr][c] = v; }
+                }
+            }
+        HIP_TRY(hipStreamSynchronize(st));
+        d_targs.release();
+        tuned = true;
+    }
+    HIP_TRY(hipEventRecord(lead->ev0, st));
+    for (int c = 0; c < kNumClasses; ++c) {
+        HIP_TRY(hipEventRecord(lead->ev_cls[c], st));
+        for (int pr = 0; pr < 2; ++pr) {
+            set_range(a, c, pr);
+            if (!a.ntasks) continue;
+            HIP_TRY(kLaunch[c](variant[pr][c], pr, a, lr, st, grid_max));
+        }
+    }
+    HIP_TRY(hipEventRecord(lead->ev_cls[kNumClasses], st));
+    HIP_TRY(hipEventRecord(lead->ev1, st));
+    for (int m = 0; m < n; ++m) {
+        tdg_plan *pl = pls[m];
+        const size_t bytes = sizeof(double) * 3 * pl->n_atoms;
+        HIP_TRY(hipMemcpyAsync(grad[m], pl->d_grad.p, bytes,
+                               ptr_kind == 0 ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+    }
+    if (ptr_kind == 0 || stats) HIP_TRY(hipStreamSynchronize(st));
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        for (int c = 0; c < kNumClasses; ++c) {
+            const long long n64 = seg_end[c][0] - seg_begin[c][0], n32 = seg_end[c][1] - seg_begin[c][1];
+            stats->class_quartets[c] = n64 + n32;
+            stats->class_fp32_quartets[c] = n32;
+            stats->fp32_quartets += n32;
+            for (int m = 0; m < n; ++m) {
+                stats->class_prim_quartets[c] += (long long)pls[m]->h_prim[c];
+                stats->prim_quartets += (long long)pls[m]->h_prim[c];
+                stats->candidates += (long long)pls[m]->h_cand[c];
+            }
+            float cm = 0.f;
+            HIP_TRY(hipEventElapsedTime(&cm, lead->ev_cls[c], lead->ev_cls[c + 1]));
+            stats->class_ms[c] = cm;
+            stats->class_variant[c] = variant[0][c] | (variant[1][c] << 1);
+        }
+        stats->quartets = total;
+        stats->ml_skipped = ml_skipped;
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, lead->ev0, lead->ev1));
+        stats->ms_kernels = ms;
+        stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return TDG_OK;
+}
+
+extern "C" {
+
+int tdg_grad_jk(tdg_plan_t *pl, const double *P0, const double *PD, const double *R, int32_t ptr_kind,
+                void *hip_stream, double *grad, tdg_stats_t *stats)
+{
+    g_err.clear();
+    if (!pl) return fail(TDG_EINVAL, "null plan");
+    if (!P0 || !PD || !R || !grad) return fail(TDG_EINVAL, "null density or output pointer");
+    if (ptr_kind != 0 && ptr_kind != 1) return fail(TDG_EINVAL, "ptr_kind must be 0 or 1");
+    return run_molecules(1, &pl, &P0, &PD, &R, ptr_kind, (hipStream_t)hip_stream, &grad, stats);
+}
+
+int tdg_grad_jk_batch(int32_t n, tdg_plan_t *const *plans, const double *const *P0, const double *const *PD,
+                      const double *const *R, int32_t ptr_kind, void *hip_stream, double *const *grad,
+                      tdg_stats_t *stats)
+{
+    g_err.clear();
+    if (n <= 0 || !plans || !P0 || !PD || !R || !grad) return fail(TDG_EINVAL, "bad batch arguments");
+    if (ptr_kind != 0 && ptr_kind != 1) return fail(TDG_EINVAL, "ptr_kind must be 0 or 1");
+    for (int m = 0; m < n; ++m) {
+        if (!plans[m] || !P0[m] || !PD[m] || !R[m] || !grad[m]) return fail(TDG_EINVAL, "null entry %d in batch", m);
+        const tdg_params_t &x = plans[m]->prm, &y = plans[0]->prm;
+        if (plans[m]->device != plans[0]->device || x.omega != y.omega || x.alpha != y.alpha || x.beta != y.beta ||
+            x.terms != y.terms || x.precision != y.precision)
+            return fail(TDG_EINVAL, "plan %d differs from plan 0 in device or method parameters", m);
+        for (int k = 0; k < m; ++k)
+            if (plans[k] == plans[m]) return fail(TDG_EINVAL, "plan %d appears twice in the batch", m);
+    }
+    return run_molecules(n, plans, P0, PD, R, ptr_kind, (hipStream_t)hip_stream, grad, stats);
+}
+
+int tdg_plan_set_screen_model(tdg_plan_t *pl, const tdg_mlp_t *model, double log10_threshold, double tau_hi)
+{
+    g_err.clear();
+    if (!pl) return fail(TDG_EINVAL, "null plan");
+    pl->ml = model;
+    pl->ml_log10 = log10_threshold;
+    pl->ml_tau_hi = tau_hi;
+    return TDG_OK;
+}
+
+int tdg_collect(tdg_plan_t *pl, const double *P0, const double *PD, const double *R, int32_t ptr_kind,
+                void *hip_stream, float *feat, float *target, int64_t cap, int64_t stride, int64_t *n_out)
+{
+    g_err.clear();
+    if (!pl || !P0 || !PD || !R || !feat || !target || !n_out || cap < 0 || stride < 1)
+        return fail(TDG_EINVAL, "bad arguments");
+    if (pl->prm.precision != 0) return fail(TDG_EINVAL, "collection needs an FP64 plan");
+    if (ptr_kind != 0 && ptr_kind != 1) return fail(TDG_EINVAL, "ptr_kind must be 0 or 1");
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipSetDevice(pl->device));
+    int rc;
+    if ((rc = prep_and_count(pl, P0, PD, R, ptr_kind, st))) return rc;
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<long long> offs(pl->item_class_off[kNumClasses]);
+    long long seg_begin[kNumClasses], total = 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+        seg_begin[c] = total;
+        const bool act = class_active(pl, c);
+        for (int k = pl->item_class_off[c]; k < pl->item_class_off[c + 1]; ++k) {
+            offs[k] = total;
+            if (act) total += pl->h_cnt[k];
+        }
+    }
+    if ((rc = pl->d_tasks.alloc(std::max<long long>(total, 1)))) return rc;
+    if (!offs.empty())
+        HIP_TRY(hipMemcpyAsync(pl->d_item_off.p, offs.data(), 8 * offs.size(), hipMemcpyHostToDevice, st));
+    ScreenArgs s = screen_args(pl);
+    s.tasks = pl->d_tasks.p;
+    for (int c = 0; c < kNumClasses; ++c) {
+        if (!class_active(pl, c)) continue;
+        screen_setup(pl, s, c);
+        hipLaunchKernelGGL(k_screen<true>, dim3((s.nbra + 3) / 4), dim3(256), 0, st, s);
+    }
+    DevBuf<double> contrib;
+    if ((rc = contrib.alloc(std::max<long long>(12 * total, 1)))) return rc;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((12 * total + 255) / 256 + 1)), dim3(256), 0, st, contrib.p, 12 * total);
+    const bool lr = (pl->prm.terms & 4) && pl->prm.beta != 0.0;
+    DerivArgs a = deriv_args(pl);
     int ncu = 256;
     {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, pl->device) == hipSuccess) ncu = prop.multiProcessorCount;
     }
-    const int grid_max = ncu * 8;
-    if (pl->prm.autotune && pl->prm.kernel_variant < 0 && !pl->tuned) {
-        // a12 autotuner: time every kernel variant of each class on this call's task list
-        // (into a scratch gradient), keep the fastest for the plan's later calls
-        if ((rc = pl->d_grad_tune.alloc((size_t)3 * pl->n_atoms))) return rc;
-        DerivArgs at = a;
-        at.grad = pl->d_grad_tune.p;
-        for (int c = 0; c < kNumClasses; ++c) {
-            const long long n = class_begin[c + 1] - class_begin[c];
-            if (!n) continue;
-            at.tasks = pl->d_tasks.p + class_begin[c];
-            at.ntasks = n;
-            float best = 1e30f;
-            for (int v = 0; v < 2; ++v) {
-                float ms = 0.f;
-                for (int rep = 0; rep < 2; ++rep) { // second launch is the measured one
-                    HIP_TRY(hipEventRecord(pl->ev_cls[0], st));
-                    HIP_TRY(launch_class(c, v, at, lr, st, grid_max));
-                    HIP_TRY(hipEventRecord(pl->ev_cls[1], st));
-                    HIP_TRY(hipEventSynchronize(pl->ev_cls[1]));
-                    HIP_TRY(hipEventElapsedTime(&ms, pl->ev_cls[0], pl->ev_cls[1]));
-                }
-                if (ms < best) { best = ms; pl->variant[c] = v; }
-            }
-        }
-        pl->tuned = true;
-    }
-    HIP_TRY(hipEventRecord(pl->ev0, st));
     for (int c = 0; c < kNumClasses; ++c) {
-        HIP_TRY(hipEventRecord(pl->ev_cls[c], st));
-        const long long n = class_begin[c + 1] - class_begin[c];
+        const long long n = (c + 1 < kNumClasses ? seg_begin[c + 1] : total) - seg_begin[c];
         if (!n) continue;
-        a.tasks = pl->d_tasks.p + class_begin[c];
+        a.tasks = pl->d_tasks.p + seg_begin[c];
         a.ntasks = n;
-        HIP_TRY(launch_class(c, pl->variant[c], a, lr, st, grid_max));
+        a.task_out = contrib.p + 12 * seg_begin[c];
+        HIP_TRY(kLaunch[c](default_variant(c), 0, a, lr, st, ncu * 8));
     }
-    HIP_TRY(hipEventRecord(pl->ev_cls[kNumClasses], st));
-    HIP_TRY(hipEventRecord(pl->ev1, st));
-    if (ptr_kind == 0) {
-        HIP_TRY(hipMemcpyAsync(grad, pl->d_grad.p, sizeof(double) * 3 * pl->n_atoms, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-    } else {
-        HIP_TRY(hipMemcpyAsync(grad, pl->d_grad.p, sizeof(double) * 3 * pl->n_atoms, hipMemcpyDeviceToDevice, st));
-    }
-    if (stats) {
-        HIP_TRY(hipStreamSynchronize(st));
-        std::memset(stats, 0, sizeof *stats);
-        for (int c = 0; c < kNumClasses; ++c) {
-            stats->class_quartets[c] = class_begin[c + 1] - class_begin[c];
-            stats->class_prim_quartets[c] = (long long)primc[c];
-            stats->prim_quartets += (long long)primc[c];
-            stats->candidates += (long long)candc[c];
-            float cm = 0.f;
-            HIP_TRY(hipEventElapsedTime(&cm, pl->ev_cls[c], pl->ev_cls[c + 1]));
-            stats->class_ms[c] = cm;
-            stats->class_variant[c] = pl->variant[c];
-        }
-        stats->quartets = total;
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
-        stats->ms_kernels = ms;
-        stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-    }
+    const long long ns = (total + stride - 1) / stride;
+    const long long nout = std::min<long long>(ns, cap);
+    if (nout > 0)
+        hipLaunchKernelGGL(k_collect, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, st, pl->d_tasks.p, total,
+                           (long long)stride, feat_args(pl), contrib.p, feat, target, (long long)cap, 0LL);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    contrib.release();
+    *n_out = nout;
     return TDG_OK;
 }
 

@@ -21,8 +21,11 @@ NUM_CLASSES = 21
 PAIR_CLASSES = ((0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2))
 CLASSES = tuple(PAIR_CLASSES[b] + PAIR_CLASSES[k] for b in range(6) for k in range(b + 1))
 
-EXPORTED = ("tdg_plan_create", "tdg_grad_jk", "tdg_plan_destroy", "tdg_plan_dims",
-            "tdg_plan_schwarz", "tdg_rys_rule", "tdg_last_error")
+EXPORTED = ("tdg_plan_create", "tdg_grad_jk", "tdg_grad_jk_batch", "tdg_plan_destroy", "tdg_plan_dims",
+            "tdg_plan_schwarz", "tdg_rys_rule", "tdg_plan_set_screen_model", "tdg_collect",
+            "tdg_mlp_create", "tdg_mlp_destroy", "tdg_mlp_nweights", "tdg_mlp_set_weights",
+            "tdg_mlp_get_weights", "tdg_mlp_forward", "tdg_mlp_grad", "tdg_mlp_train_step",
+            "tdg_last_error")
 
 
 class TdgError(RuntimeError):
@@ -42,7 +45,8 @@ class Basis(C.Structure):
 class Params(C.Structure):
     _fields_ = [("omega", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
                 ("schwarz_tol", C.c_double), ("precision", C.c_int32), ("terms", C.c_int32),
-                ("autotune", C.c_int32), ("kernel_variant", C.c_int32)]
+                ("autotune", C.c_int32), ("kernel_variant", C.c_int32),
+                ("mixed_tau64", C.c_double), ("mixed_p64", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -50,7 +54,10 @@ class Stats(C.Structure):
                 ("class_quartets", C.c_int64 * NUM_CLASSES),
                 ("class_prim_quartets", C.c_int64 * NUM_CLASSES),
                 ("class_ms", C.c_double * NUM_CLASSES),
-                ("class_variant", C.c_int32 * NUM_CLASSES), ("ms_total", C.c_double),
+                ("class_variant", C.c_int32 * NUM_CLASSES),
+                ("fp32_quartets", C.c_int64), ("ml_skipped", C.c_int64),
+                ("class_fp32_quartets", C.c_int64 * NUM_CLASSES),
+                ("ms_total", C.c_double),
                 ("ms_kernels", C.c_double)]
 
     def as_dict(self):
@@ -58,6 +65,8 @@ class Stats(C.Structure):
                 "candidates": self.candidates, "class_quartets": list(self.class_quartets),
                 "class_prim_quartets": list(self.class_prim_quartets),
                 "class_ms": list(self.class_ms), "class_variant": list(self.class_variant),
+                "fp32_quartets": self.fp32_quartets, "ml_skipped": self.ml_skipped,
+                "class_fp32_quartets": list(self.class_fp32_quartets),
                 "ms_total": self.ms_total,
                 "ms_kernels": self.ms_kernels}
 
@@ -78,10 +87,22 @@ def lib():
         vp = C.c_void_p
         L.tdg_plan_create.argtypes = [C.POINTER(Basis), C.POINTER(Params), C.c_int, C.POINTER(vp)]
         L.tdg_grad_jk.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, C.POINTER(Stats)]
+        L.tdg_grad_jk_batch.argtypes = [C.c_int32, vp, vp, vp, vp, C.c_int32, vp, vp, C.POINTER(Stats)]
         L.tdg_plan_destroy.argtypes = [vp]
         L.tdg_plan_dims.argtypes = [vp, vp, vp, vp]
         L.tdg_plan_schwarz.argtypes = [vp, vp]
         L.tdg_rys_rule.argtypes = [C.c_int32, C.c_double, vp, vp]
+        L.tdg_plan_set_screen_model.argtypes = [vp, vp, C.c_double, C.c_double]
+        L.tdg_collect.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, C.c_int64, C.c_int64,
+                                  C.POINTER(C.c_int64)]
+        L.tdg_mlp_create.argtypes = [C.c_int, C.c_uint64, C.POINTER(vp)]
+        L.tdg_mlp_destroy.argtypes = [vp]
+        L.tdg_mlp_nweights.argtypes = []
+        L.tdg_mlp_set_weights.argtypes = [vp, vp]
+        L.tdg_mlp_get_weights.argtypes = [vp, vp]
+        L.tdg_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.tdg_mlp_grad.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
+        L.tdg_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, vp, vp]
         L.tdg_last_error.restype = C.c_char_p
         for f in EXPORTED[:-1]:
             getattr(L, f).restype = C.c_int
@@ -102,7 +123,8 @@ class Plan:
     """A plan for one molecule (geometry + basis); see tdg_plan_create."""
 
     def __init__(self, mol, omega=None, alpha=None, beta=None, schwarz_tol=1e-10, terms=TERMS_ALL,
-                 precision=0, device=0, autotune=True, kernel_variant=-1):
+                 precision=0, device=0, autotune=True, kernel_variant=-1, mixed_tau64=1e-7,
+                 mixed_p64=float("inf")):
         self._keep = [np.ascontiguousarray(mol.coords, dtype=np.float64)]
         for name in ("shell_atom", "shell_l", "shell_nprim", "shell_prim_off", "shell_ao_off"):
             self._keep.append(np.ascontiguousarray(getattr(mol, name), dtype=np.int32))
@@ -113,7 +135,7 @@ class Plan:
                   _ptr(k[4]), _ptr(k[5]), mol.n_prims, _ptr(k[6]), _ptr(k[7]))
         self.params = Params(mol.omega if omega is None else omega, mol.alpha if alpha is None else alpha,
                              mol.beta if beta is None else beta, schwarz_tol, precision, terms,
-                             1 if autotune else 0, kernel_variant)
+                             1 if autotune else 0, kernel_variant, mixed_tau64, mixed_p64)
         h = C.c_void_p()
         _check(lib().tdg_plan_create(C.byref(b), C.byref(self.params), device, C.byref(h)))
         self._h = h
@@ -151,6 +173,23 @@ class Plan:
                                  C.byref(st) if stats else None))
         return (out, st.as_dict()) if stats else out
 
+    def set_screen_model(self, model, log10_threshold=-12.0, tau_hi=1e-6):
+        """Attach a trained Estimator (or None) as a veto after the Schwarz screening."""
+        self._model = model
+        _check(lib().tdg_plan_set_screen_model(self._h, model._h if model is not None else None,
+                                               log10_threshold, tau_hi))
+
+    def collect(self, P0, PD, R, feat, target, stride=1, stream=None):
+        """Device densities (torch, float64) -> features/targets written into the device tensors
+        feat [cap, 16] and target [cap] (float32); returns the number of samples."""
+        import torch
+        n = C.c_int64()
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        _check(lib().tdg_collect(self._h, P0.data_ptr(), PD.data_ptr(), R.data_ptr(), 1, s,
+                                 feat.data_ptr(), target.data_ptr(), feat.shape[0], stride,
+                                 C.byref(n)))
+        return n.value
+
     def grad_device(self, P0, PD, R, out, stream=None, stats=False):
         """torch CUDA/HIP tensors (float64, contiguous) on the plan's device; asynchronous
         on `stream` (default: torch's current stream) unless stats are requested."""
@@ -166,6 +205,101 @@ class Plan:
         _check(lib().tdg_grad_jk(self._h, P0.data_ptr(), PD.data_ptr(), R.data_ptr(), 1, s,
                                  out.data_ptr(), C.byref(st) if stats else None))
         return st.as_dict() if stats else None
+
+
+class Estimator:
+    """The quartet-contribution network (tdg_mlp_*): BF16 matrix-core forward/backward,
+    FP32 master weights, Adam."""
+
+    def __init__(self, seed=0, device=0):
+        h = C.c_void_p()
+        _check(lib().tdg_mlp_create(device, seed, C.byref(h)))
+        self._h = h
+        self.nweights = lib().tdg_mlp_nweights()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tdg_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def weights(self):
+        w = np.zeros(self.nweights, dtype=np.float32)
+        _check(lib().tdg_mlp_get_weights(self._h, _ptr(w)))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.shape == (self.nweights,)
+        _check(lib().tdg_mlp_set_weights(self._h, _ptr(w)))
+
+    def forward(self, X, out=None, stream=None):
+        import torch
+        out = out if out is not None else torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        _check(lib().tdg_mlp_forward(self._h, X.data_ptr(), X.shape[0], out.data_ptr(), s))
+        return out
+
+    def grad(self, X, Y, stream=None):
+        import torch
+        g = np.zeros(self.nweights, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        _check(lib().tdg_mlp_grad(self._h, X.data_ptr(), Y.data_ptr(), X.shape[0], _ptr(g), _ptr(loss), s))
+        return float(loss[0]), g
+
+    def train_step(self, X, Y, lr, want_loss=False, stream=None):
+        import torch
+        loss = np.zeros(1, dtype=np.float32)
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        _check(lib().tdg_mlp_train_step(self._h, X.data_ptr(), Y.data_ptr(), X.shape[0], lr,
+                                        _ptr(loss) if want_loss else None, s))
+        return float(loss[0]) if want_loss else None
+
+
+def grad_batch(plans, dens, stats=False):
+    """Host numpy densities [(P0, PD, R), ...] for plans [...] -> list of host gradients,
+    evaluated in one batched pass (tdg_grad_jk_batch)."""
+    n = len(plans)
+    keep = []
+    ptrs = [(C.c_void_p * n)() for _ in range(3)]
+    outs = []
+    for m, (p, d) in enumerate(zip(plans, dens)):
+        for k in range(3):
+            x = np.ascontiguousarray(d[k], dtype=np.float64)
+            if x.shape != (p.n_bf, p.n_bf):
+                raise ValueError("density shape mismatch")
+            keep.append(x)
+            ptrs[k][m] = _ptr(x)
+        outs.append(np.zeros((p.n_atoms, 3)))
+    hp = (C.c_void_p * n)(*[p._h.value for p in plans])
+    go = (C.c_void_p * n)(*[_ptr(o) for o in outs])
+    st = Stats()
+    _check(lib().tdg_grad_jk_batch(n, hp, ptrs[0], ptrs[1], ptrs[2], 0, None, go,
+                                   C.byref(st) if stats else None))
+    return (outs, st.as_dict()) if stats else outs
+
+
+def grad_batch_device(plans, dens, outs, stream=None, stats=False):
+    """torch device tensors: dens [(P0, PD, R), ...], outs [(n_atoms, 3), ...]; asynchronous."""
+    import torch
+    n = len(plans)
+    ptrs = [(C.c_void_p * n)() for _ in range(3)]
+    for m, d in enumerate(dens):
+        for k in range(3):
+            ptrs[k][m] = d[k].data_ptr()
+    hp = (C.c_void_p * n)(*[p._h.value for p in plans])
+    go = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    st = Stats()
+    _check(lib().tdg_grad_jk_batch(n, hp, ptrs[0], ptrs[1], ptrs[2], 1, s, go,
+                                   C.byref(st) if stats else None))
+    return st.as_dict() if stats else None
 
 
 def rys_rule(n, T):

@@ -172,7 +172,7 @@ def test_both_kernel_variants_all_classes(tdg, oracle_lib, mol0, variant):
     for m in (mol0, molecules.small_mixed()):
         p = tdg.Plan(m, schwarz_tol=0.0, kernel_variant=variant)
         g, st = p.grad(m.P0, m.PD, m.R, stats=True)
-        assert all(v == variant for v, n in zip(st["class_variant"], st["class_quartets"]) if n)
+        assert all((v & 1) == variant for v, n in zip(st["class_variant"], st["class_quartets"]) if n)
         ref = oracle_lib.grad(m)
         err = np.abs(g - ref).max()
         _say("  max-abs", err)
@@ -190,3 +190,96 @@ def test_autotuned_plan_is_stable(tdg, mol0, oracle_lib):
     assert s1["class_variant"] == s2["class_variant"]
     assert np.abs(g1 - g2).max() <= 1e-12
     assert np.abs(g2 - oracle_lib.grad(mol0, tau=1e-10)).max() <= TOL
+
+
+# ------------------------------------------------------------------ mixed precision
+MIXED_TOL = 1e-6
+
+
+@pytest.mark.parametrize("variant", [-1, 0, 1])
+def test_mixed_precision_small(tdg, oracle_lib, mol0, variant):
+    """FP32 2D integrals (FP64 roots, prefactors, sums) within 1e-6 of the FP64 oracle,
+    with every quartet routed to FP32 (thresholds at infinity) and with the defaults."""
+    for m in (mol0, molecules.small_mixed()):
+        ref = oracle_lib.grad(m)
+        for kw in ({}, {"mixed_tau64": math.inf, "mixed_p64": math.inf}):
+            p = tdg.Plan(m, schwarz_tol=0.0, precision=1, kernel_variant=variant, **kw)
+            g, st = p.grad(m.P0, m.PD, m.R, stats=True)
+            err = np.abs(g - ref).max()
+            _say("mixed", variant, kw, "fp32 quartets", st["fp32_quartets"], "of", st["quartets"], "err", err)
+            assert err <= MIXED_TOL
+        if kw:
+            assert st["fp32_quartets"] == st["quartets"]
+
+
+def test_mixed_all_fp64_routing_equals_fp64(tdg, mol0):
+    """With both thresholds at zero every quartet stays FP64: same result as precision 0."""
+    p64 = tdg.Plan(mol0, schwarz_tol=1e-10)
+    pm = tdg.Plan(mol0, schwarz_tol=1e-10, precision=1, mixed_tau64=0.0, mixed_p64=0.0)
+    g1 = p64.grad(mol0.P0, mol0.PD, mol0.R)
+    g2, st = pm.grad(mol0.P0, mol0.PD, mol0.R, stats=True)
+    assert st["fp32_quartets"] == 0
+    assert np.abs(g1 - g2).max() <= 1e-12
+
+
+def test_chain60_mixed_against_stored_oracle(tdg):
+    from paper_2407_16586_amd import synth
+    ref = json.load(open(os.path.join(HERE, "golden", "chain60_tau1e-10.json")))
+    m = synth.config1()
+    p = tdg.Plan(m, schwarz_tol=ref["tau"], precision=1)
+    g, st = p.grad(m.P0, m.PD, m.R, stats=True)
+    err = np.abs(g - np.array(ref["grad"])).max()
+    _say("chain60 mixed max-abs", err, "fp32 fraction", st["fp32_quartets"] / st["quartets"])
+    assert err <= MIXED_TOL
+
+
+# ------------------------------------------------------------------ batched launch
+def _batch_molecules():
+    from paper_2407_16586_amd import synth
+    mols = [synth.random_molecule(nh, nl, seed=100 + k) for k, (nh, nl) in
+            enumerate([(2, 4), (1, 2), (3, 3), (1, 0), (2, 1), (0, 3)])]
+    mols.append(molecules.small_mixed(4))
+    return mols
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_matches_oracle_and_single_calls(tdg, oracle_lib, precision):
+    """Several molecules of different sizes (one without any d shell, one with a single
+    atom) in one batched pass: each gradient equals the oracle's and the single-call result."""
+    mols = _batch_molecules()
+    plans = [tdg.Plan(m, schwarz_tol=1e-10, precision=precision) for m in mols]
+    outs, st = tdg.grad_batch(plans, [(m.P0, m.PD, m.R) for m in mols], stats=True)
+    tol = TOL if precision == 0 else MIXED_TOL
+    for m, g in zip(mols, outs):
+        ref = oracle_lib.grad(m, tau=1e-10)
+        err = np.abs(g - ref).max()
+        _say("batch", m.name, m.n_bf, "err", err)
+        assert err <= tol
+    singles = [tdg.Plan(m, schwarz_tol=1e-10, precision=precision) for m in mols]
+    for m, p, g in zip(mols, singles, outs):
+        assert np.abs(p.grad(m.P0, m.PD, m.R) - g).max() <= 1e-11
+    assert st["quartets"] == sum(p.grad(m.P0, m.PD, m.R, stats=True)[1]["quartets"] for m, p in zip(mols, singles))
+
+
+def test_batch_repeated_and_device(tdg, oracle_lib):
+    import torch
+    mols = _batch_molecules()[:4]
+    plans = [tdg.Plan(m, schwarz_tol=1e-10) for m in mols]
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    dens = [(t(m.P0), t(m.PD), t(m.R)) for m in mols]
+    outs = [torch.zeros((m.n_atoms, 3), dtype=torch.float64, device=dev) for m in mols]
+    for _ in range(3):
+        tdg.grad_batch_device(plans, dens, outs)
+    torch.cuda.synchronize()
+    for m, o in zip(mols, outs):
+        assert np.abs(o.cpu().numpy() - oracle_lib.grad(m, tau=1e-10)).max() <= TOL
+
+
+def test_batch_argument_errors(tdg, mol0):
+    p = tdg.Plan(mol0)
+    with pytest.raises(tdg.TdgError):
+        tdg.grad_batch([p, p], [(mol0.P0, mol0.PD, mol0.R)] * 2)
+    q = tdg.Plan(mol0, omega=0.4)
+    with pytest.raises(tdg.TdgError):
+        tdg.grad_batch([p, q], [(mol0.P0, mol0.PD, mol0.R)] * 2)
