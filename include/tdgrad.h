@@ -94,12 +94,17 @@ typedef struct {
                            sqrt(max zeta) over its primitive pairs */
     int32_t terms;      /* bit 1: Coulomb-type (J) terms, bit 2: full-range exchange (alpha),
                            bit 4: long-range exchange (beta); 7 = all */
-    int32_t autotune;   /* 1: on the plan's first tdg_grad_jk call, time every kernel variant of
-                           each angular class on that call's tasks and keep the fastest */
+    int32_t autotune;   /* 1: on the plan's first tdg_grad_jk call, time the kernel variants 0
+                           and 1 of each angular class on that call's tasks and keep the fastest;
+                           in mixed mode also run a class's FP32-routed quartets in FP64 (one
+                           launch for the class) when that measures faster than the split */
     int32_t kernel_variant; /* -1: per-class default or autotuned choice; 0: team-per-quartet
-                               kernels for every class; 1: wavefront-per-quartet kernels */
+                               kernels (vertical recursion + transfers); 1: wavefront-per-quartet
+                               kernels; 2: team-per-quartet kernels with direct four-centre
+                               tables (FP32 team kernels always use these) */
     double mixed_tau64; /* mixed mode: FP32 only when bound * f_ab * f_cd is below this */
     double mixed_p64;   /* mixed mode: pairs with a primitive exponent sum >= this stay FP64 */
+    int64_t max_tasks;  /* screened quartets held at once (chunking of large systems); 0 = 2^31 */
 } tdg_params_t;
 
 /* Per-call statistics (optional output). */
@@ -110,13 +115,16 @@ typedef struct {
     int64_t class_quartets[21];/* per angular class, in the library's class order */
     int64_t class_prim_quartets[21];
     double class_ms[21];       /* derivative-kernel time per class (HIP events on the call's stream) */
-    int32_t class_variant[21]; /* kernel variants per class: bit 0 the FP64 list's, bit 1 the FP32 list's
-                                  (0 team per quartet, 1 wavefront per quartet) */
-    int64_t fp32_quartets;     /* mixed mode: quartets evaluated with FP32 2D integrals */
+    int32_t class_variant[21]; /* kernel variant per class: bits 0-1 the FP64 list's, bits 2-3 the
+                                  FP32 list's (0 team, 1 wavefront, 2 team with direct tables);
+                                  bit 4 set: the FP32-routed quartets ran in FP64 */
+    int64_t fp32_quartets;     /* mixed mode: quartets evaluated with FP32 2D integrals (those
+                                  routed to FP32 in classes that run the FP32 kernels) */
     int64_t ml_skipped;        /* quartets vetoed by the contribution estimator */
+    int64_t chunks;            /* number of task-list chunks the call was split into */
     int64_t class_fp32_quartets[21];
     double ms_total;           /* wall time of the call (host clock, synchronised) */
-    double ms_kernels;         /* summed derivative-kernel time (HIP events) */
+    double ms_kernels;         /* summed derivative-kernel time (HIP events), all chunks */
 } tdg_stats_t;
 
 /* Build a plan for one geometry and basis on HIP device `device`:

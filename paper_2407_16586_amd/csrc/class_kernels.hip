@@ -34,11 +34,14 @@ hipError_t go(int variant, const tdg::DerivArgs &a, hipStream_t st, int grid_max
 {
     using namespace tdg;
     const size_t dyn = a.lds_atoms ? (size_t)3 * a.n_atoms * sizeof(double) : 0;
-    if (variant == 0) {
+    if (variant == 0 || variant == 2) {
         using K = DerivClass<LA, LB, LC, LD, LR, F>;
         const long long blocks = (a.ntasks + K::TPB - 1) / K::TPB;
         const int grid = (int)(blocks < grid_max ? blocks : grid_max);
-        hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+        if (variant == 2 || sizeof(F) != sizeof(double))
+            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, true>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+        else
+            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, false>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
     } else {
         using K = WaveClass<LA, LB, LC, LD, LR, F>;
         const long long blocks = (a.ntasks + K::WAVES - 1) / K::WAVES;

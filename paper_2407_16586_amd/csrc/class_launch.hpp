@@ -6,7 +6,8 @@
 
 namespace tdg {
 struct DerivArgs;
-// variant 0: team of lanes per shell quartet, 1: wavefront per shell quartet;
+// variant 0: team of lanes per shell quartet (vertical recursion + transfers in FP64),
+// 1: wavefront per shell quartet, 2: team of lanes with direct four-centre tables;
 // prec 0: FP64 2D integrals, 1: FP32 2D integrals (FP64 roots and sums)
 using LaunchFn = hipError_t (*)(int variant, int prec, const DerivArgs &a, bool lr, hipStream_t st, int grid_max);
 } // namespace tdg

@@ -191,7 +191,12 @@ struct DerivClass {
     static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     static constexpr int N = NA * NB * NC * ND;
     static constexpr int GSTRIDE = NSET * N + 1;  // odd stride: teams start in different banks
-    static constexpr int LDS_G_BYTES = 40 * 1024;
+    // Rys table of the class staged in LDS when it fits beside Gamma (n <= 3 roots); the
+    // static LDS (Gamma + table) stays within 40 KB so that with the per-atom array
+    // (<= 24 KB) a block needs at most 64 KB
+    static constexpr bool TAB_LDS = NR <= 3;
+    static constexpr int TAB_N = TAB_LDS ? rys_table_size<NR>() : 1;
+    static constexpr int LDS_G_BYTES = 40 * 1024 - (TAB_LDS ? TAB_N * 8 : 0);
     static constexpr int GB = (int)sizeof(F);
     static constexpr int TPB_LDS = LDS_G_BYTES / (GSTRIDE * GB) > 0 ? LDS_G_BYTES / (GSTRIDE * GB) : 1;
     static constexpr int TPB = TPW * 4 < TPB_LDS ? TPW * 4 : TPB_LDS;
@@ -220,19 +225,37 @@ __device__ __forceinline__ void gamma_sym(const DerivArgs &a, int mu, int nu, in
 
 // F: type of the 2D integrals, derivative products and per-primitive partial sums
 // (double, or float for the mixed-precision route); roots, weights, prefactors and
-// the running sums are FP64 in both.
-template <int LA, int LB, int LC, int LD, bool LR, typename F>
+// the running sums are FP64 in both.  DIRECT: base-index tables from the direct
+// four-centre recurrence (always used for float) instead of the vertical recursion
+// plus transfers.
+template <int LA, int LB, int LC, int LD, bool LR, typename F, bool DIRECT = (sizeof(F) != sizeof(double))>
 __global__ void __launch_bounds__((DerivClass<LA, LB, LC, LD, LR, F>::BLOCK))
 k_deriv(const DerivArgs a)
 {
     using K = DerivClass<LA, LB, LC, LD, LR, F>;
     constexpr int NR = K::NR, TEAM = K::TEAM, TPW = K::TPW, TPB = K::TPB;
     constexpr int NA = K::NA, NB = K::NB, NC = K::NC, ND = K::ND, N = K::N;
+    // FP32 route: the per-primitive partial sums go to the FP64 sums after every
+    // (a, b) component pair (2) or every a component (1) when those groups hold
+    // several components, so no FP32 sum runs over more than NC*ND (NB*NC*ND) terms
+    constexpr int FLUSH = sizeof(F) == sizeof(double) ? 0 : (NC * ND >= 6 ? 2 : (NB * NC * ND >= 6 ? 1 : 0));
+    auto flush = [](double *acc, F *pacc) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            acc[k] += double(pacc[k]);
+            pacc[k] = F(0);
+        }
+    };
     extern __shared__ double s_atoms[];
     __shared__ F s_gam[TPB * K::GSTRIDE];
+    __shared__ double s_rys[K::TAB_N];
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int tw = lane / TEAM, r = lane % TEAM;
+    if constexpr (K::TAB_LDS) {
+        rys_table_to_lds<NR>(s_rys);
+        __syncthreads();
+    }
     const int team = wave * TPW + tw;
     const bool lane_ok = (tw < TPW) && (team < TPB);
     const int set = r / NR, ir = r % NR;
@@ -304,7 +327,8 @@ k_deriv(const DerivArgs a)
                         Tr *= eta;
                     }
                     double u, w;
-                    rys_root<NR>(Tr, ir, u, w);
+                    if constexpr (K::TAB_LDS) rys_root_lds<NR>(s_rys, Tr, ir, u, w);
+                    else rys_root<NR>(Tr, ir, u, w);
                     if (LR && set) {
                         u *= eta;
                         w *= sqrt(eta);
@@ -318,7 +342,7 @@ k_deriv(const DerivArgs a)
                     F pacc[9];
 #pragma unroll
                     for (int k = 0; k < 9; ++k) pacc[k] = F(0);
-                    if constexpr (sizeof(F) == sizeof(double)) {
+                    if constexpr (!DIRECT) {
                         Rys2D<LA + LB + 1, LC + LD + 1, LA, LB + 1, LD + 1, F> g[3];
 #pragma unroll
                         for (int d = 0; d < 3; ++d) {
@@ -369,9 +393,9 @@ k_deriv(const DerivArgs a)
                                                              F(zd2 * CDx), F(dc.g2), F(dc.g3), F(dc.g4));
                         }
 #pragma unroll
-                        for (int ia = 0; ia < NA; ++ia)
+                        for (int ia = 0; ia < NA; ++ia) {
 #pragma unroll
-                            for (int ib2 = 0; ib2 < NB; ++ib2)
+                            for (int ib2 = 0; ib2 < NB; ++ib2) {
 #pragma unroll
                                 for (int ic = 0; ic < NC; ++ic)
 #pragma unroll
@@ -393,6 +417,11 @@ k_deriv(const DerivArgs a)
                                         pacc[2] += txy * T[2][NBASE + e[2]]; pacc[5] += txy * T[2][2 * NBASE + e[2]];
                                         pacc[8] += txy * T[2][3 * NBASE + e[2]];
                                     }
+                                // FP32 partial sums span at most a few dozen components
+                                if constexpr (FLUSH == 2) flush(acc, pacc);
+                            }
+                            if constexpr (FLUSH == 1) flush(acc, pacc);
+                        }
                     }
 #pragma unroll
                     for (int k = 0; k < 9; ++k) acc[k] += double(pacc[k]);

@@ -91,6 +91,41 @@ __device__ __forceinline__ void rys_root(double T, int r, double &u, double &w)
     }
 }
 
+// Same rule with the polynomial table of N roots read from a copy in LDS
+// (rys_table_to_lds<N> fills it: RYS_NINT * 2N * RYS_NCOEF doubles).
+template <int N> constexpr int rys_table_size() { return RYS_NINT * 2 * N * RYS_NCOEF; }
+
+template <int N>
+__device__ __forceinline__ void rys_table_to_lds(double *lds)
+{
+    const double *src = rys_poly<N>();
+    for (int i = threadIdx.x; i < rys_table_size<N>(); i += blockDim.x) lds[i] = src[i];
+}
+
+template <int N>
+__device__ __forceinline__ void rys_root_lds(const double *tab, double T, int r, double &u, double &w)
+{
+    if (T < RYS_TMAX) {
+        const int j = (int)(T * (1.0 / RYS_WIDTH));
+        const double x = T - RYS_WIDTH * (j + 0.5);
+        const double *cu = tab + ((j * 2 * N) + r) * RYS_NCOEF;
+        const double *cw = cu + N * RYS_NCOEF;
+        double a = cu[RYS_NCOEF - 1], b = cw[RYS_NCOEF - 1];
+#pragma unroll
+        for (int k = RYS_NCOEF - 2; k >= 0; --k) {
+            a = fma(a, x, cu[k]);
+            b = fma(b, x, cw[k]);
+        }
+        u = a;
+        w = b;
+    } else {
+        const double it = 1.0 / T;
+        const double xh = rys_hx<N>()[r];
+        u = xh * xh * it;
+        w = rys_hw<N>()[r] * sqrt(it);
+    }
+}
+
 __device__ __forceinline__ void rys_root_rt(int n, double T, int r, double &u, double &w)
 {
     switch (n) {

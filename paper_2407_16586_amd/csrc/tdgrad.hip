@@ -142,7 +142,9 @@ struct tdg_plan {
     std::vector<int> item_class_off;       // [22] offset of each class's items
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ev_cls[kNumClasses + 1] = {};
-    int variant[2][kNumClasses];           // kernel variant per (precision, class): 0 team, 1 wavefront
+    int variant[2][kNumClasses];           // kernel variant per (precision, class): 0 team, 1 wavefront, 2 direct team
+    int split[kNumClasses];                // 1: the FP32-routed quartets of the class run in FP32; 0: the
+                                           // whole class runs in FP64 (measured faster by the autotuner)
     std::vector<double> pair_pmax;         // largest primitive exponent sum of each sorted pair
     DevBuf<double> d_pair_pmax;
     std::vector<double> pair_famp;         // FP32 error-amplification proxy of each sorted pair
@@ -156,6 +158,7 @@ struct tdg_plan {
     DevBuf<int> d_bmol;
     DevBuf<DerivArgs> d_bargs;
     int bvariant[2][kNumClasses];
+    int bsplit[kNumClasses];
     bool btuned = false;
     // learned screening (a13): estimator and thresholds (log10 of the contribution)
     const tdg_mlp *ml = nullptr;
@@ -815,6 +818,7 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
         for (int c = 0; c < kNumClasses; ++c)
             pl->variant[pr][c] = pl->bvariant[pr][c] =
                 pl->prm.kernel_variant >= 0 ? pl->prm.kernel_variant : default_variant(c);
+    for (int c = 0; c < kNumClasses; ++c) pl->split[c] = pl->bsplit[c] = 1;
     HIP_TRY(hipDeviceSynchronize());
     return TDG_OK;
 }
@@ -854,8 +858,8 @@ int tdg_plan_create(const tdg_basis_t *basis, const tdg_params_t *params, int de
     if (params->precision != 0 && params->precision != 1)
         return fail(TDG_EUNSUPPORTED, "precision mode %d not available", params->precision);
     if ((params->terms & 4) && !(params->omega > 0.0)) return fail(TDG_EINVAL, "long-range term needs omega > 0");
-    if (params->kernel_variant < -1 || params->kernel_variant > 1)
-        return fail(TDG_EINVAL, "kernel_variant must be -1, 0 or 1");
+    if (params->kernel_variant < -1 || params->kernel_variant > 2)
+        return fail(TDG_EINVAL, "kernel_variant must be -1, 0, 1 or 2");
     int ndev = 0;
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(TDG_EINVAL, "device %d not present (%d devices)", device, ndev);
@@ -1096,6 +1100,13 @@ static DerivArgs deriv_args(tdg_plan *pl)
     return a;
 }
 
+// Screened tasks of one chunk: a contiguous range of screening items (single molecule)
+// or every item of every molecule (batched), laid out per (class, precision) segment.
+struct Chunk {
+    long long seg_begin[kNumClasses][2], seg_end[kNumClasses][2];
+    long long total = 0;
+};
+
 static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, const double *const *PD,
                          const double *const *R, int ptr_kind, hipStream_t st, double *const *grad, tdg_stats_t *stats)
 {
@@ -1107,74 +1118,31 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
         if ((rc = prep_and_count(pls[m], P0[m], PD[m], R[m], ptr_kind, st))) return rc;
     HIP_TRY(hipStreamSynchronize(st));
     const bool batched = n > 1;
-    // layout: segment (class c, precision pr) = molecules in order, each [items in order]
-    long long seg_begin[kNumClasses][2], seg_end[kNumClasses][2];
-    long long total = 0;
-    std::vector<std::vector<long long>> offs(n), offs32(n);
-    for (int m = 0; m < n; ++m) {
-        offs[m].assign(pls[m]->item_class_off[kNumClasses], 0);
-        offs32[m].assign(pls[m]->item_class_off[kNumClasses], 0);
-    }
-    for (int c = 0; c < kNumClasses; ++c)
-        for (int pr = 0; pr < 2; ++pr) {
-            seg_begin[c][pr] = total;
-            for (int m = 0; m < n; ++m) {
-                tdg_plan *pl = pls[m];
-                const bool act = class_active(pl, c);
-                for (int k = pl->item_class_off[c]; k < pl->item_class_off[c + 1]; ++k) {
-                    if (pr == 0) offs[m][k] = total; else offs32[m][k] = total;
-                    if (act) total += pr == 0 ? pl->h_cnt[k] : pl->h_cnt32[k];
-                }
-            }
-            seg_end[c][pr] = total;
-        }
-    int2 *tasks;
-    int *task_mol = nullptr;
+    // chunks of screening items (one molecule): at most max_tasks survivors each, so the
+    // task list of a large system is never materialised whole
+    std::vector<std::pair<int, int>> chunks;
     if (batched) {
-        if ((rc = lead->d_btasks.alloc(std::max<long long>(total, 1))) ||
-            (rc = lead->d_bmol.alloc(std::max<long long>(total, 1))))
-            return rc;
-        tasks = lead->d_btasks.p;
-        task_mol = lead->d_bmol.p;
+        chunks.push_back({0, 0});
     } else {
-        if ((rc = lead->d_tasks.alloc(std::max<long long>(total, 1)))) return rc;
-        tasks = lead->d_tasks.p;
-    }
-    for (int m = 0; m < n; ++m) {
-        tdg_plan *pl = pls[m];
-        const int nitems = pl->item_class_off[kNumClasses];
-        if (nitems)
-            HIP_TRY(hipMemcpyAsync(pl->d_item_off.p, offs[m].data(), 8 * nitems, hipMemcpyHostToDevice, st));
-        if (nitems && pl->prm.precision == 1)
-            HIP_TRY(hipMemcpyAsync(pl->d_item_off32.p, offs32[m].data(), 8 * nitems, hipMemcpyHostToDevice, st));
-        ScreenArgs s = screen_args(pl);
-        s.tasks = tasks;
-        s.task_mol = task_mol;
-        s.mol = m;
-        for (int c = 0; c < kNumClasses; ++c) {
-            if (!class_active(pl, c)) continue;
-            screen_setup(pl, s, c);
-            hipLaunchKernelGGL(k_screen<true>, dim3((s.nbra + 3) / 4), dim3(256), 0, st, s);
+        const long long cap = lead->prm.max_tasks > 0 ? lead->prm.max_tasks : (1LL << 31);
+        const int nitems = lead->item_class_off[kNumClasses];
+        std::vector<char> act(kNumClasses);
+        for (int c = 0; c < kNumClasses; ++c) act[c] = class_active(lead, c);
+        int k0 = 0, c = 0;
+        long long acc = 0;
+        for (int k = 0; k < nitems; ++k) {
+            while (k >= lead->item_class_off[c + 1]) ++c;
+            const long long v = act[c] ? (long long)lead->h_cnt[k] + lead->h_cnt32[k] : 0;
+            if (acc + v > cap && k > k0) {
+                chunks.push_back({k0, k});
+                k0 = k;
+                acc = 0;
+            }
+            acc += v;
         }
+        chunks.push_back({k0, nitems});
     }
-    HIP_TRY(hipGetLastError());
-    long long ml_skipped = 0;
-    const long long screened = total;
-    if (!batched && lead->ml) {
-        if ((rc = ml_filter(lead, tasks, seg_begin, seg_end, st, ml_skipped))) return rc;
-        total = screened - ml_skipped;
-    }
-    // a5-a10
     const bool lr = (lead->prm.terms & 4) && lead->prm.beta != 0.0;
-    DerivArgs a = deriv_args(lead);
-    if (batched) {
-        std::vector<DerivArgs> margs(n);
-        for (int m = 0; m < n; ++m) margs[m] = deriv_args(pls[m]);
-        if ((rc = lead->d_bargs.alloc(n))) return rc;
-        HIP_TRY(hipMemcpyAsync(lead->d_bargs.p, margs.data(), sizeof(DerivArgs) * n, hipMemcpyHostToDevice, st));
-        a.batch = lead->d_bargs.p;
-        a.lds_atoms = 0; // gradients of many molecules: direct FP64 atomics
-    }
     int ncu = 256;
     {
         hipDeviceProp_t prop;
@@ -1182,41 +1150,127 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
     }
     const int grid_max = ncu * 8;
     int(*variant)[kNumClasses] = batched ? lead->bvariant : lead->variant;
+    int *split = batched ? lead->bsplit : lead->split;
     bool &tuned = batched ? lead->btuned : lead->tuned;
-    auto set_range = [&](DerivArgs &x, int c, int pr) {
-        x.tasks = tasks + seg_begin[c][pr];
-        x.task_mol = task_mol ? task_mol + seg_begin[c][pr] : nullptr;
-        x.ntasks = seg_end[c][pr] - seg_begin[c][pr];
-    };
-    if (lead->prm.autotune && lead->prm.kernel_variant < 0 && !tuned) {
-        // a12 autotuner: time the kernel variants of each (class, precision) on this call's
-        // task list (into scratch gradients) and keep the fastest for later calls.  The
-        // wavefront design is a candidate for classes with >= 27 components.
-        std::vector<DerivArgs> targs;
+    long long tot_quartets = 0, tot_fp32 = 0, ml_skipped = 0;
+    long long cls_q[kNumClasses] = {0}, cls_q32[kNumClasses] = {0};
+    double cls_ms[kNumClasses] = {0.0}, kern_ms = 0.0;
+    for (size_t ci = 0; ci < chunks.size(); ++ci) {
+        const int K0 = chunks[ci].first, K1 = chunks[ci].second;
+        Chunk ch;
+        std::vector<std::vector<long long>> offs(n), offs32(n);
+        for (int m = 0; m < n; ++m) {
+            offs[m].assign(pls[m]->item_class_off[kNumClasses], 0);
+            offs32[m].assign(pls[m]->item_class_off[kNumClasses], 0);
+        }
+        long long total = 0;
+        for (int c = 0; c < kNumClasses; ++c)
+            for (int pr = 0; pr < 2; ++pr) {
+                ch.seg_begin[c][pr] = total;
+                for (int m = 0; m < n; ++m) {
+                    tdg_plan *pl = pls[m];
+                    const bool act = class_active(pl, c);
+                    int lo = pl->item_class_off[c], hi = pl->item_class_off[c + 1];
+                    if (!batched) { lo = std::max(lo, K0); hi = std::min(hi, K1); }
+                    for (int k = lo; k < hi; ++k) {
+                        if (pr == 0) offs[m][k] = total; else offs32[m][k] = total;
+                        if (act) total += pr == 0 ? pl->h_cnt[k] : pl->h_cnt32[k];
+                    }
+                }
+                ch.seg_end[c][pr] = total;
+            }
+        int2 *tasks;
+        int *task_mol = nullptr;
         if (batched) {
-            targs.resize(n);
-            for (int m = 0; m < n; ++m) {
-                targs[m] = deriv_args(pls[m]);
-                if ((rc = pls[m]->d_grad_tune.alloc((size_t)3 * pls[m]->n_atoms))) return rc;
-                targs[m].grad = pls[m]->d_grad_tune.p;
+            if ((rc = lead->d_btasks.alloc(std::max<long long>(total, 1))) ||
+                (rc = lead->d_bmol.alloc(std::max<long long>(total, 1))))
+                return rc;
+            tasks = lead->d_btasks.p;
+            task_mol = lead->d_bmol.p;
+        } else {
+            if ((rc = lead->d_tasks.alloc(std::max<long long>(total, 1)))) return rc;
+            tasks = lead->d_tasks.p;
+        }
+        for (int m = 0; m < n; ++m) {
+            tdg_plan *pl = pls[m];
+            const int i0 = batched ? 0 : K0, i1 = batched ? pl->item_class_off[kNumClasses] : K1;
+            if (i1 > i0) {
+                HIP_TRY(hipMemcpyAsync(pl->d_item_off.p + i0, offs[m].data() + i0, 8 * (i1 - i0), hipMemcpyHostToDevice, st));
+                if (pl->prm.precision == 1)
+                    HIP_TRY(hipMemcpyAsync(pl->d_item_off32.p + i0, offs32[m].data() + i0, 8 * (i1 - i0),
+                                           hipMemcpyHostToDevice, st));
+            }
+            ScreenArgs s = screen_args(pl);
+            s.tasks = tasks;
+            s.task_mol = task_mol;
+            s.mol = m;
+            for (int c = 0; c < kNumClasses; ++c) {
+                if (!class_active(pl, c)) continue;
+                screen_setup(pl, s, c);
+                const int lo = std::max(pl->item_class_off[c], i0), hi = std::min(pl->item_class_off[c + 1], i1);
+                if (hi <= lo) continue;
+                const int skip = lo - pl->item_class_off[c];
+                s.bra0 += skip;
+                s.nbra = hi - lo;
+                s.item_cnt += skip; s.item_off += skip; s.item_cnt32 += skip; s.item_off32 += skip;
+                hipLaunchKernelGGL(k_screen<true>, dim3((s.nbra + 3) / 4), dim3(256), 0, st, s);
             }
         }
-        DerivArgs at = a;
-        DevBuf<DerivArgs> d_targs;
-        if (batched) {
-            if ((rc = d_targs.alloc(n))) return rc;
-            HIP_TRY(hipMemcpyAsync(d_targs.p, targs.data(), sizeof(DerivArgs) * n, hipMemcpyHostToDevice, st));
-            at.batch = d_targs.p;
-        } else {
-            if ((rc = lead->d_grad_tune.alloc((size_t)3 * lead->n_atoms))) return rc;
-            at.grad = lead->d_grad_tune.p;
+        HIP_TRY(hipGetLastError());
+        if (!batched && lead->ml) {
+            long long sk = 0;
+            if ((rc = ml_filter(lead, tasks, ch.seg_begin, ch.seg_end, st, sk))) return rc;
+            ml_skipped += sk;
         }
-        for (int pr = 0; pr < 2; ++pr)
-            for (int c = 0; c < kNumClasses; ++c) {
-                set_range(at, c, pr);
-                if (!at.ntasks || class_ncomp(c) < 27) continue;
-                float best = 1e30f;
+        // a5-a10
+        DerivArgs a = deriv_args(lead);
+        if (batched) {
+            std::vector<DerivArgs> margs(n);
+            for (int m = 0; m < n; ++m) margs[m] = deriv_args(pls[m]);
+            if ((rc = lead->d_bargs.alloc(n))) return rc;
+            HIP_TRY(hipMemcpyAsync(lead->d_bargs.p, margs.data(), sizeof(DerivArgs) * n, hipMemcpyHostToDevice, st));
+            a.batch = lead->d_bargs.p;
+            a.lds_atoms = 0; // gradients of many molecules: direct FP64 atomics
+        }
+        auto set_range = [&](DerivArgs &x, int c, int pr) {
+            x.tasks = tasks + ch.seg_begin[c][pr];
+            x.task_mol = task_mol ? task_mol + ch.seg_begin[c][pr] : nullptr;
+            x.ntasks = ch.seg_end[c][pr] - ch.seg_begin[c][pr];
+        };
+        if (lead->prm.autotune && lead->prm.kernel_variant < 0 && !tuned) {
+            // a12 autotuner: time the kernel variants of each class on this call's task list
+            // (into scratch gradients) and keep the fastest for later calls.  The wavefront
+            // design is a candidate for classes with >= 27 components.  With the mixed route
+            // it also decides the precision per class: the FP32-routed quartets run in FP32
+            // only where FP64 over the whole class measures slower.
+            std::vector<DerivArgs> targs;
+            DerivArgs at = a;
+            DevBuf<DerivArgs> d_targs;
+            if (batched) {
+                targs.resize(n);
+                for (int m = 0; m < n; ++m) {
+                    targs[m] = deriv_args(pls[m]);
+                    if ((rc = pls[m]->d_grad_tune.alloc((size_t)3 * pls[m]->n_atoms))) return rc;
+                    targs[m].grad = pls[m]->d_grad_tune.p;
+                }
+                if ((rc = d_targs.alloc(n))) return rc;
+                HIP_TRY(hipMemcpyAsync(d_targs.p, targs.data(), sizeof(DerivArgs) * n, hipMemcpyHostToDevice, st));
+                at.batch = d_targs.p;
+            } else {
+                if ((rc = lead->d_grad_tune.alloc((size_t)3 * lead->n_atoms))) return rc;
+                at.grad = lead->d_grad_tune.p;
+            }
+            // fastest variant of precision pr over tasks [b, e): (ms, variant)
+            auto best_of = [&](int c, int pr, long long b, long long e, float &best, int &bv) -> int {
+                best = 0.f;
+                bv = variant[pr][c];
+                if (e <= b) return TDG_OK;
+                at.tasks = tasks + b;
+                at.task_mol = task_mol ? task_mol + b : nullptr;
+                at.ntasks = e - b;
+                best = 1e30f;
                 for (int v = 0; v < 2; ++v) {
+                    if (v == 1 && class_ncomp(c) < 27) continue;
                     float ms = 0.f;
                     for (int rep = 0; rep < 2; ++rep) { // the second launch is the measured one
                         HIP_TRY(hipEventRecord(lead->ev_cls[0], st));
@@ -1225,24 +1279,70 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                         HIP_TRY(hipEventSynchronize(lead->ev_cls[1]));
                         HIP_TRY(hipEventElapsedTime(&ms, lead->ev_cls[0], lead->ev_cls[1]));
                     }
-                    if (ms < best) { best = ms; variant[pr][c] = v; }
+                    if (ms < best) { best = ms; bv = v; }
+                }
+                return TDG_OK;
+            };
+            for (int c = 0; c < kNumClasses; ++c) {
+                const long long b0 = ch.seg_begin[c][0], e0 = ch.seg_end[c][0];
+                const long long b1 = ch.seg_begin[c][1], e1 = ch.seg_end[c][1];
+                float t_all = 0.f, t64 = 0.f, t32 = 0.f;
+                int v_all = 0, v64 = 0, v32 = 0;
+                if ((rc = best_of(c, 0, b0, e1, t_all, v_all))) return rc;
+                if (e1 > b1) {
+                    if ((rc = best_of(c, 0, b0, e0, t64, v64)) || (rc = best_of(c, 1, b1, e1, t32, v32))) return rc;
+                }
+                if (e1 > b1 && t64 + t32 < t_all) {
+                    split[c] = 1;
+                    variant[0][c] = v64;
+                    variant[1][c] = v32;
+                } else {
+                    split[c] = e1 > b1 ? 0 : split[c];
+                    variant[0][c] = v_all;
                 }
             }
-        HIP_TRY(hipStreamSynchronize(st));
-        d_targs.release();
-        tuned = true;
-    }
-    HIP_TRY(hipEventRecord(lead->ev0, st));
-    for (int c = 0; c < kNumClasses; ++c) {
-        HIP_TRY(hipEventRecord(lead->ev_cls[c], st));
-        for (int pr = 0; pr < 2; ++pr) {
-            set_range(a, c, pr);
-            if (!a.ntasks) continue;
-            HIP_TRY(kLaunch[c](variant[pr][c], pr, a, lr, st, grid_max));
+            HIP_TRY(hipStreamSynchronize(st));
+            d_targs.release();
+            tuned = true;
+        }
+        HIP_TRY(hipEventRecord(lead->ev0, st));
+        for (int c = 0; c < kNumClasses; ++c) {
+            HIP_TRY(hipEventRecord(lead->ev_cls[c], st));
+            if (!split[c]) { // the whole class (both routes) in FP64, one launch
+                a.tasks = tasks + ch.seg_begin[c][0];
+                a.task_mol = task_mol ? task_mol + ch.seg_begin[c][0] : nullptr;
+                a.ntasks = ch.seg_end[c][1] - ch.seg_begin[c][0];
+                if (a.ntasks) HIP_TRY(kLaunch[c](variant[0][c], 0, a, lr, st, grid_max));
+                continue;
+            }
+            for (int pr = 0; pr < 2; ++pr) {
+                set_range(a, c, pr);
+                if (!a.ntasks) continue;
+                HIP_TRY(kLaunch[c](variant[pr][c], pr, a, lr, st, grid_max));
+            }
+        }
+        HIP_TRY(hipEventRecord(lead->ev_cls[kNumClasses], st));
+        HIP_TRY(hipEventRecord(lead->ev1, st));
+        for (int c = 0; c < kNumClasses; ++c) {
+            const long long n64 = ch.seg_end[c][0] - ch.seg_begin[c][0], n32 = ch.seg_end[c][1] - ch.seg_begin[c][1];
+            cls_q[c] += n64 + n32;
+            cls_q32[c] += split[c] ? n32 : 0;
+            tot_quartets += n64 + n32;
+            tot_fp32 += split[c] ? n32 : 0;
+        }
+        if (stats || chunks.size() > 1) {
+            // per-chunk timing (the next chunk reuses the event objects)
+            HIP_TRY(hipEventSynchronize(lead->ev1));
+            for (int c = 0; c < kNumClasses; ++c) {
+                float cm = 0.f;
+                HIP_TRY(hipEventElapsedTime(&cm, lead->ev_cls[c], lead->ev_cls[c + 1]));
+                cls_ms[c] += cm;
+            }
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, lead->ev0, lead->ev1));
+            kern_ms += ms;
         }
     }
-    HIP_TRY(hipEventRecord(lead->ev_cls[kNumClasses], st));
-    HIP_TRY(hipEventRecord(lead->ev1, st));
     for (int m = 0; m < n; ++m) {
         tdg_plan *pl = pls[m];
         const size_t bytes = sizeof(double) * 3 * pl->n_atoms;
@@ -1253,25 +1353,21 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
     if (stats) {
         std::memset(stats, 0, sizeof *stats);
         for (int c = 0; c < kNumClasses; ++c) {
-            const long long n64 = seg_end[c][0] - seg_begin[c][0], n32 = seg_end[c][1] - seg_begin[c][1];
-            stats->class_quartets[c] = n64 + n32;
-            stats->class_fp32_quartets[c] = n32;
-            stats->fp32_quartets += n32;
+            stats->class_quartets[c] = cls_q[c];
+            stats->class_fp32_quartets[c] = cls_q32[c];
             for (int m = 0; m < n; ++m) {
                 stats->class_prim_quartets[c] += (long long)pls[m]->h_prim[c];
                 stats->prim_quartets += (long long)pls[m]->h_prim[c];
                 stats->candidates += (long long)pls[m]->h_cand[c];
             }
-            float cm = 0.f;
-            HIP_TRY(hipEventElapsedTime(&cm, lead->ev_cls[c], lead->ev_cls[c + 1]));
-            stats->class_ms[c] = cm;
-            stats->class_variant[c] = variant[0][c] | (variant[1][c] << 1);
+            stats->class_ms[c] = cls_ms[c];
+            stats->class_variant[c] = variant[0][c] | (variant[1][c] << 2) | (split[c] ? 0 : 16);
         }
-        stats->quartets = total;
+        stats->quartets = tot_quartets;
+        stats->fp32_quartets = tot_fp32;
         stats->ml_skipped = ml_skipped;
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, lead->ev0, lead->ev1));
-        stats->ms_kernels = ms;
+        stats->chunks = (int64_t)chunks.size();
+        stats->ms_kernels = kern_ms;
         stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     }
     return TDG_OK;

@@ -268,27 +268,33 @@ def config2(n_mol: int = 64, with_dens: bool = True) -> list[Molecule]:
             for i, n in enumerate(sizes)]
 
 
-def config3(with_dens: bool = True) -> Molecule:
-    """133 waters on a 5.9 bohr cubic lattice with +-0.4 bohr jitter, random orientations."""
-    rng = np.random.default_rng(BASE_SEED + 3)
+def water_cluster(n_waters: int, seed: int, with_dens: bool = True) -> Molecule:
+    """n waters on the sites of a 6x6x4 cubic lattice (5.9 bohr) nearest its centroid, +-0.4 bohr
+    jitter, O-H 1.81 bohr, HOH 104.5 degrees, random orientations; 5 occupied orbitals per water."""
+    rng = np.random.default_rng(seed)
     g = np.array([(i, j, k) for i in range(6) for j in range(6) for k in range(4)], float) * 5.9
     cen = g.mean(axis=0)
     order = np.argsort(np.linalg.norm(g - cen, axis=1), kind="stable")
-    sites = g[order[:133]]
+    sites = g[order[:n_waters]]
     roh, ang = 1.81, math.radians(104.5)
     body = np.array([[0.0, 0.0, 0.0],
                      [roh * math.sin(ang / 2), 0.0, roh * math.cos(ang / 2)],
                      [-roh * math.sin(ang / 2), 0.0, roh * math.cos(ang / 2)]])
     pts, Z = [], []
-    for s in sites:
+    for s_ in sites:
         q, r = np.linalg.qr(rng.standard_normal((3, 3)))
         q = q * np.sign(np.diag(r))[None, :]
-        o = s + rng.uniform(-0.4, 0.4, size=3)
+        o = s_ + rng.uniform(-0.4, 0.4, size=3)
         for a, z in zip(body, (8, 1, 1)):
             pts.append(o + q @ a)
             Z.append(z)
-    return _assemble("133 waters", rng, np.array(pts), np.array(Z), n_occ=665,
+    return _assemble(f"{n_waters} waters", rng, np.array(pts), np.array(Z), n_occ=5 * n_waters,
                      with_dens=with_dens)
+
+
+def config3(with_dens: bool = True) -> Molecule:
+    """133 waters on a 5.9 bohr cubic lattice with +-0.4 bohr jitter, random orientations."""
+    return water_cluster(133, BASE_SEED + 3, with_dens)
 
 
 def config4(with_dens: bool = True) -> Molecule:

@@ -46,7 +46,7 @@ class Params(C.Structure):
     _fields_ = [("omega", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
                 ("schwarz_tol", C.c_double), ("precision", C.c_int32), ("terms", C.c_int32),
                 ("autotune", C.c_int32), ("kernel_variant", C.c_int32),
-                ("mixed_tau64", C.c_double), ("mixed_p64", C.c_double)]
+                ("mixed_tau64", C.c_double), ("mixed_p64", C.c_double), ("max_tasks", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -55,7 +55,7 @@ class Stats(C.Structure):
                 ("class_prim_quartets", C.c_int64 * NUM_CLASSES),
                 ("class_ms", C.c_double * NUM_CLASSES),
                 ("class_variant", C.c_int32 * NUM_CLASSES),
-                ("fp32_quartets", C.c_int64), ("ml_skipped", C.c_int64),
+                ("fp32_quartets", C.c_int64), ("ml_skipped", C.c_int64), ("chunks", C.c_int64),
                 ("class_fp32_quartets", C.c_int64 * NUM_CLASSES),
                 ("ms_total", C.c_double),
                 ("ms_kernels", C.c_double)]
@@ -66,6 +66,7 @@ class Stats(C.Structure):
                 "class_prim_quartets": list(self.class_prim_quartets),
                 "class_ms": list(self.class_ms), "class_variant": list(self.class_variant),
                 "fp32_quartets": self.fp32_quartets, "ml_skipped": self.ml_skipped,
+                "chunks": self.chunks,
                 "class_fp32_quartets": list(self.class_fp32_quartets),
                 "ms_total": self.ms_total,
                 "ms_kernels": self.ms_kernels}
@@ -124,7 +125,7 @@ class Plan:
 
     def __init__(self, mol, omega=None, alpha=None, beta=None, schwarz_tol=1e-10, terms=TERMS_ALL,
                  precision=0, device=0, autotune=True, kernel_variant=-1, mixed_tau64=1e-7,
-                 mixed_p64=float("inf")):
+                 mixed_p64=float("inf"), max_tasks=0):
         self._keep = [np.ascontiguousarray(mol.coords, dtype=np.float64)]
         for name in ("shell_atom", "shell_l", "shell_nprim", "shell_prim_off", "shell_ao_off"):
             self._keep.append(np.ascontiguousarray(getattr(mol, name), dtype=np.int32))
@@ -135,7 +136,7 @@ class Plan:
                   _ptr(k[4]), _ptr(k[5]), mol.n_prims, _ptr(k[6]), _ptr(k[7]))
         self.params = Params(mol.omega if omega is None else omega, mol.alpha if alpha is None else alpha,
                              mol.beta if beta is None else beta, schwarz_tol, precision, terms,
-                             1 if autotune else 0, kernel_variant, mixed_tau64, mixed_p64)
+                             1 if autotune else 0, kernel_variant, mixed_tau64, mixed_p64, max_tasks)
         h = C.c_void_p()
         _check(lib().tdg_plan_create(C.byref(b), C.byref(self.params), device, C.byref(h)))
         self._h = h

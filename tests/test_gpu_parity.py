@@ -164,15 +164,15 @@ def test_chain60_against_stored_oracle(tdg, variant):
     assert err <= TOL
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_both_kernel_variants_all_classes(tdg, oracle_lib, mol0, variant):
-    """Each of the two kernel designs (team per quartet, wavefront per quartet), forced on
-    every angular class, matches the oracle."""
+    """Each kernel design (team per quartet with transfers, wavefront per quartet, team per
+    quartet with direct four-centre tables), forced on every angular class, matches the oracle."""
     _say("variant", variant)
     for m in (mol0, molecules.small_mixed()):
         p = tdg.Plan(m, schwarz_tol=0.0, kernel_variant=variant)
         g, st = p.grad(m.P0, m.PD, m.R, stats=True)
-        assert all((v & 1) == variant for v, n in zip(st["class_variant"], st["class_quartets"]) if n)
+        assert all((v & 3) == variant for v, n in zip(st["class_variant"], st["class_quartets"]) if n)
         ref = oracle_lib.grad(m)
         err = np.abs(g - ref).max()
         _say("  max-abs", err)
@@ -208,8 +208,8 @@ def test_mixed_precision_small(tdg, oracle_lib, mol0, variant):
             err = np.abs(g - ref).max()
             _say("mixed", variant, kw, "fp32 quartets", st["fp32_quartets"], "of", st["quartets"], "err", err)
             assert err <= MIXED_TOL
-        if kw:
-            assert st["fp32_quartets"] == st["quartets"]
+            if kw and variant >= 0:  # fixed variants honour the routing exactly
+                assert st["fp32_quartets"] == st["quartets"]
 
 
 def test_mixed_all_fp64_routing_equals_fp64(tdg, mol0):
@@ -283,3 +283,19 @@ def test_batch_argument_errors(tdg, mol0):
     q = tdg.Plan(mol0, omega=0.4)
     with pytest.raises(tdg.TdgError):
         tdg.grad_batch([p, q], [(mol0.P0, mol0.PD, mol0.R)] * 2)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_chunked_task_lists(tdg, oracle_lib, precision):
+    """A task list split into many chunks (max_tasks small) gives the unchunked result."""
+    m = molecules.small_mixed(6)
+    ref = oracle_lib.grad(m, tau=1e-10)
+    one = tdg.Plan(m, schwarz_tol=1e-10, precision=precision)
+    g1, s1 = one.grad(m.P0, m.PD, m.R, stats=True)
+    many = tdg.Plan(m, schwarz_tol=1e-10, precision=precision, max_tasks=97)
+    g2, s2 = many.grad(m.P0, m.PD, m.R, stats=True)
+    _say("chunks", s2["chunks"], "quartets", s2["quartets"], s1["quartets"])
+    assert s1["chunks"] == 1 and s2["chunks"] > 5
+    assert s2["quartets"] == s1["quartets"]
+    assert np.abs(g2 - g1).max() <= 1e-12
+    assert np.abs(g2 - ref).max() <= (TOL if precision == 0 else MIXED_TOL)
