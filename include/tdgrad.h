@@ -94,14 +94,17 @@ typedef struct {
                            sqrt(max zeta) over its primitive pairs */
     int32_t terms;      /* bit 1: Coulomb-type (J) terms, bit 2: full-range exchange (alpha),
                            bit 4: long-range exchange (beta); 7 = all */
-    int32_t autotune;   /* 1: on the plan's first tdg_grad_jk call, time the kernel variants 0
-                           and 1 of each angular class on that call's tasks and keep the fastest;
+    int32_t autotune;   /* 1: on the plan's first tdg_grad_jk call, time the kernel variants
+                           of each angular class on that call's tasks and keep the fastest;
                            in mixed mode also run a class's FP32-routed quartets in FP64 (one
                            launch for the class) when that measures faster than the split */
     int32_t kernel_variant; /* -1: per-class default or autotuned choice; 0: team-per-quartet
-                               kernels (vertical recursion + transfers); 1: wavefront-per-quartet
-                               kernels; 2: team-per-quartet kernels with direct four-centre
-                               tables (FP32 team kernels always use these) */
+                               kernels (FP64: vertical recursion + transfers; FP32: direct
+                               four-centre derivative tables); 1: wavefront-per-quartet kernels;
+                               2: team-per-quartet kernels with direct four-centre base tables
+                               and the collapsed contraction.  Variant 0 is offered only for
+                               classes whose variant-0 kernel needs no scratch memory; there
+                               variant 2 runs instead (stats report the variant that ran) */
     double mixed_tau64; /* mixed mode: FP32 only when bound * f_ab * f_cd is below this */
     double mixed_p64;   /* mixed mode: pairs with a primitive exponent sum >= this stay FP64 */
     int64_t max_tasks;  /* screened quartets held at once (chunking of large systems); 0 = 2^31 */
@@ -116,7 +119,7 @@ typedef struct {
     int64_t class_prim_quartets[21];
     double class_ms[21];       /* derivative-kernel time per class (HIP events on the call's stream) */
     int32_t class_variant[21]; /* kernel variant per class: bits 0-1 the FP64 list's, bits 2-3 the
-                                  FP32 list's (0 team, 1 wavefront, 2 team with direct tables);
+                                  FP32 list's (0 team, 1 wavefront, 2 collapsed team);
                                   bit 4 set: the FP32-routed quartets ran in FP64 */
     int64_t fp32_quartets;     /* mixed mode: quartets evaluated with FP32 2D integrals (those
                                   routed to FP32 in classes that run the FP32 kernels) */

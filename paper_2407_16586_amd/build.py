@@ -28,22 +28,45 @@ def table(force: bool = False) -> str:
     return TABLE
 
 
-def build(extra_flags: list[str] | None = None, verbose: bool = False, jobs: int | None = None) -> str:
-    """Compile the host runtime and the 21 per-class kernel units in parallel, then link."""
+# sources each object depends on (for incremental builds)
+_DEV = ["tdg_device.hpp", "rys_table.inc"]
+_DEPS = {
+    "tdgrad": ["tdgrad.hip", "class_launch.hpp", "deriv_kernel.hpp", "mlp.hpp", "../../include/tdgrad.h"] + _DEV,
+    "mlp": ["mlp.hip", "mlp.hpp", "../../include/tdgrad.h"],
+    "class": ["class_kernels.hip", "class_launch.hpp", "deriv_kernel.hpp", "deriv_wave.hpp"] + _DEV,
+}
+
+
+def build(extra_flags: list[str] | None = None, verbose: bool = False, jobs: int | None = None,
+          incremental: bool = False) -> str:
+    """Compile the host runtime and the 21 per-class kernel units in parallel, then link.
+    incremental=True keeps the objects in _build/ and recompiles only those whose
+    sources changed since (same flags assumed)."""
     import concurrent.futures as cf
     import tempfile
 
     table()
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     flags = [f for f in HIPCC_FLAGS if f != "-shared"] + list(extra_flags or [])
-    with tempfile.TemporaryDirectory(prefix="tdgrad_build_") as tmpd:
-        jobs_ = [(MAIN, os.path.join(tmpd, "tdgrad.o"), []),
-                 (os.path.join(CSRC, "mlp.hip"), os.path.join(tmpd, "mlp.o"), [])]
+    tmp_ctx = tempfile.TemporaryDirectory(prefix="tdgrad_build_")
+    with tmp_ctx as tmpd:
+        odir = os.path.join(os.path.dirname(CSRC), "_build") if incremental else tmpd
+        os.makedirs(odir, exist_ok=True)
+        jobs_ = [(MAIN, os.path.join(odir, "tdgrad.o"), [], "tdgrad"),
+                 (os.path.join(CSRC, "mlp.hip"), os.path.join(odir, "mlp.o"), [], "mlp")]
         for c in range(NUM_CLASSES):
-            jobs_.append((CLASS_SRC, os.path.join(tmpd, f"class_{c}.o"), [f"-DTDG_CLASS={c}"]))
+            jobs_.append((CLASS_SRC, os.path.join(odir, f"class_{c}.o"), [f"-DTDG_CLASS={c}"], "class"))
+
+        def stale(obj, kind):
+            if not incremental or not os.path.exists(obj):
+                return True
+            t = os.path.getmtime(obj)
+            return any(os.path.getmtime(os.path.join(CSRC, d)) > t for d in _DEPS[kind])
 
         def compile_one(job):
-            src, obj, defs = job
+            src, obj, defs, kind = job
+            if not stale(obj, kind):
+                return 0, "", obj
             cmd = [hipcc, *flags, *defs, "-c", "-o", obj, src]
             if verbose:
                 print(" ".join(cmd), flush=True)

@@ -38,10 +38,12 @@ hipError_t go(int variant, const tdg::DerivArgs &a, hipStream_t st, int grid_max
         using K = DerivClass<LA, LB, LC, LD, LR, F>;
         const long long blocks = (a.ntasks + K::TPB - 1) / K::TPB;
         const int grid = (int)(blocks < grid_max ? blocks : grid_max);
-        if (variant == 2 || sizeof(F) != sizeof(double))
-            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, true>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+        if (variant == 2)
+            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 2>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+        else if constexpr (sizeof(F) != sizeof(double))
+            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 1>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
         else
-            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, false>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 0>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
     } else {
         using K = WaveClass<LA, LB, LC, LD, LR, F>;
         const long long blocks = (a.ntasks + K::WAVES - 1) / K::WAVES;
@@ -50,7 +52,25 @@ hipError_t go(int variant, const tdg::DerivArgs &a, hipStream_t st, int grid_max
     }
     return hipGetLastError();
 }
+template <bool LR, typename F>
+const void *kernel_ptr(int variant)
+{
+    using namespace tdg;
+    if (variant == 1) return reinterpret_cast<const void *>(&k_deriv_wave<LA, LB, LC, LD, LR, F>);
+    if (variant == 2) return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 2>);
+    if constexpr (sizeof(F) != sizeof(double)) return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 1>);
+    else return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 0>);
+}
 } // namespace
+
+size_t TDG_SCRATCH_NAME(TDG_CLASS)(int variant, int prec, bool lr)
+{
+    const void *fn = prec ? (lr ? kernel_ptr<true, float>(variant) : kernel_ptr<false, float>(variant))
+                          : (lr ? kernel_ptr<true, double>(variant) : kernel_ptr<false, double>(variant));
+    hipFuncAttributes attr{};
+    if (hipFuncGetAttributes(&attr, fn) != hipSuccess) return (size_t)-1;
+    return attr.localSizeBytes;
+}
 
 hipError_t TDG_LAUNCH_NAME(TDG_CLASS)(int variant, int prec, const tdg::DerivArgs &a, bool lr, hipStream_t st,
                                       int grid_max)

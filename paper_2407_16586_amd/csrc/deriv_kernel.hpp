@@ -12,6 +12,7 @@ struct DerivArgs {
     const int *shell_ao;    // [n_shells]
     const int *pair_sa, *pair_sb, *pair_ppoff, *pair_npp; // sorted shell pairs
     const double *pp_p, *pp_Px, *pp_Py, *pp_Pz, *pp_c, *pp_za, *pp_zb; // primitive pairs
+    const double *pp_ip;    // 1/p of each primitive pair
     const double *Pn, *Dn, *Rn; // densities with the angular normalisation folded in
     int n_bf;
     const int2 *tasks;      // (bra pair, ket pair) of this class
@@ -98,30 +99,28 @@ struct DirectCoef {
 };
 
 __device__ __forceinline__ DirectCoef direct_coef(double za, double zb, double zc, double zd, double p, double q,
-                                                  double u, double ipq, double B10, double B01, double B00)
+                                                  double ip, double iq, double u, double ipq, double B10, double B01,
+                                                  double B00)
 {
     DirectCoef c;
     c.e2 = 2.0 * zb * B10;
-    c.e3 = -za / p - zb * q * u * ipq / p;
+    c.e3 = -(za + zb * q * u * ipq) * ip;
     c.e4 = 2.0 * zb * B00;
-    c.f2 = -zd / q - zc * p * u * ipq / q;
+    c.f2 = -(zd + zc * p * u * ipq) * iq;
     c.f3 = 2.0 * zc * B01;
     c.f4 = 2.0 * zc * B00;
     c.g2 = 2.0 * zd * B01;
-    c.g3 = -zc / q - zd * p * u * ipq / q;
+    c.g3 = -(zc + zd * p * u * ipq) * iq;
     c.g4 = 2.0 * zd * B00;
     return c;
 }
 
-// out[0][e] = I, out[1][e] = dB, out[2][e] = dC, out[3][e] = dD for the base index
-// e = ((i*(lb+1)+j)*(lc+1)+k)*(ld+1)+l; stride between the four kinds is NBASE.
-template <int LA, int LB, int LC, int LD, typename F, typename OUT>
-__device__ __forceinline__ void direct_tables(OUT &out, F I0, F CA, F CB, F CC, F CDd, F B10, F B01, F B00, F e1, F e2,
-                                              F e3, F e4, F f1, F f2, F f3, F f4, F g1, F g2, F g3, F g4)
+// Base-range 2D integrals I[e], e = ((i*(lb+1)+j)*(lc+1)+k)*(ld+1)+l, by the direct
+// four-centre recurrence above.
+template <int LA, int LB, int LC, int LD, typename F>
+__device__ __forceinline__ void direct_base(F *I, F I0, F CA, F CB, F CC, F CDd, F B10, F B01, F B00)
 {
     constexpr int NB1 = LB + 1, NC1 = LC + 1, ND1 = LD + 1;
-    constexpr int NBASE = (LA + 1) * NB1 * NC1 * ND1;
-    F I[NBASE];
 #define IX(i, j, k, l) I[(((i) * NB1 + (j)) * NC1 + (k)) * ND1 + (l)]
 #pragma unroll
     for (int i = 0; i <= LA; ++i)
@@ -159,6 +158,20 @@ __device__ __forceinline__ void direct_tables(OUT &out, F I0, F CA, F CB, F CC, 
                     }
                     IX(i, j, k, l) = v;
                 }
+#undef IX
+}
+
+// out[0][e] = I, out[1][e] = dB, out[2][e] = dC, out[3][e] = dD for the base index
+// e = ((i*(lb+1)+j)*(lc+1)+k)*(ld+1)+l; stride between the four kinds is NBASE.
+template <int LA, int LB, int LC, int LD, typename F, typename OUT>
+__device__ __forceinline__ void direct_tables(OUT &out, F I0, F CA, F CB, F CC, F CDd, F B10, F B01, F B00, F e1, F e2,
+                                              F e3, F e4, F f1, F f2, F f3, F f4, F g1, F g2, F g3, F g4)
+{
+    constexpr int NB1 = LB + 1, NC1 = LC + 1, ND1 = LD + 1;
+    constexpr int NBASE = (LA + 1) * NB1 * NC1 * ND1;
+    F I[NBASE];
+    direct_base<LA, LB, LC, LD, F>(I, I0, CA, CB, CC, CDd, B10, B01, B00);
+#define IX(i, j, k, l) I[(((i) * NB1 + (j)) * NC1 + (k)) * ND1 + (l)]
 #pragma unroll
     for (int i = 0; i <= LA; ++i)
 #pragma unroll
@@ -179,6 +192,41 @@ __device__ __forceinline__ void direct_tables(OUT &out, F I0, F CA, F CB, F CC, 
                     out[3 * NBASE + e] = g1 * v + g2 * km + g3 * lm + g4 * (im + jm);
                 }
 #undef IX
+}
+
+// Collapsed contraction of one root.  With H_x[e] = sum over the components whose
+// x index quadruple is e of Gamma * I_y * I_z (and H_y, H_z alike), the nine
+// derivative sums of the root are
+//   dB_d = e1_d S0 + e2 Si + e3 Sj + e4 (Sk + Sl)
+//   dC_d = f1_d S0 + f2 Sk + f3 Sl + f4 (Si + Sj)
+//   dD_d = g1_d S0 + g2 Sk + g3 Sl + g4 (Si + Sj)
+// with S0 = sum_e H_d[e] I_d[e] and Si = sum_e H_d[e] i I_d[e - 1_i] (Sj, Sk, Sl
+// alike), since the direct derivative tables are those combinations of base
+// entries.  The five S sums per direction leave the working precision F here.
+template <int LA, int LB, int LC, int LD, typename F>
+__device__ __forceinline__ void collapse_sums(const F *H, const F *I, double S[5])
+{
+    constexpr int NB1 = LB + 1, NC1 = LC + 1, ND1 = LD + 1;
+    F s0 = F(0), si = F(0), sj = F(0), sk = F(0), sl = F(0);
+#define IX(i, j, k, l) I[(((i) * NB1 + (j)) * NC1 + (k)) * ND1 + (l)]
+#pragma unroll
+    for (int i = 0; i <= LA; ++i)
+#pragma unroll
+        for (int j = 0; j <= LB; ++j)
+#pragma unroll
+            for (int k = 0; k <= LC; ++k)
+#pragma unroll
+                for (int l = 0; l <= LD; ++l) {
+                    const int e = ((i * NB1 + j) * NC1 + k) * ND1 + l;
+                    const F h = H[e];
+                    s0 += h * I[e];
+                    if (i) si += (F(i) * h) * IX(i ? i - 1 : 0, j, k, l);
+                    if (j) sj += (F(j) * h) * IX(i, j ? j - 1 : 0, k, l);
+                    if (k) sk += (F(k) * h) * IX(i, j, k ? k - 1 : 0, l);
+                    if (l) sl += (F(l) * h) * IX(i, j, k, l ? l - 1 : 0);
+                }
+#undef IX
+    S[0] = double(s0); S[1] = double(si); S[2] = double(sj); S[3] = double(sk); S[4] = double(sl);
 }
 
 template <int LA, int LB, int LC, int LD, bool LR, typename F = double>
@@ -225,10 +273,10 @@ __device__ __forceinline__ void gamma_sym(const DerivArgs &a, int mu, int nu, in
 
 // F: type of the 2D integrals, derivative products and per-primitive partial sums
 // (double, or float for the mixed-precision route); roots, weights, prefactors and
-// the running sums are FP64 in both.  DIRECT: base-index tables from the direct
-// four-centre recurrence (always used for float) instead of the vertical recursion
-// plus transfers.
-template <int LA, int LB, int LC, int LD, bool LR, typename F, bool DIRECT = (sizeof(F) != sizeof(double))>
+// the running sums are FP64 in both.  MODE 0: vertical recursion plus transfers
+// (FP64 only); 1: derivative tables from the direct four-centre recurrence; 2: the
+// direct base tables with the collapsed contraction (collapse_sums).
+template <int LA, int LB, int LC, int LD, bool LR, typename F, int MODE>
 __global__ void __launch_bounds__((DerivClass<LA, LB, LC, LD, LR, F>::BLOCK))
 k_deriv(const DerivArgs a)
 {
@@ -238,7 +286,7 @@ k_deriv(const DerivArgs a)
     // FP32 route: the per-primitive partial sums go to the FP64 sums after every
     // (a, b) component pair (2) or every a component (1) when those groups hold
     // several components, so no FP32 sum runs over more than NC*ND (NB*NC*ND) terms
-    constexpr int FLUSH = sizeof(F) == sizeof(double) ? 0 : (NC * ND >= 6 ? 2 : (NB * NC * ND >= 6 ? 1 : 0));
+    constexpr int FLUSH = (sizeof(F) == sizeof(double) || MODE != 1) ? 0 : (NC * ND >= 6 ? 2 : (NB * NC * ND >= 6 ? 1 : 0));
     auto flush = [](double *acc, F *pacc) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
@@ -265,7 +313,7 @@ k_deriv(const DerivArgs a)
         for (int i = tid; i < 3 * a.n_atoms; i += blockDim.x) s_atoms[i] = 0.0;
         __syncthreads();
     }
-    const double om2 = a.omega * a.omega;
+    const double iom2 = LR ? 1.0 / (a.omega * a.omega) : 0.0;
     const long long stride = (long long)gridDim.x * TPB;
     for (long long base = (long long)blockIdx.x * TPB; base < a.ntasks; base += stride) {
         const long long t = base + team;
@@ -305,15 +353,22 @@ k_deriv(const DerivArgs a)
             }
             const int pb0 = M.pair_ppoff[bra], nbp = M.pair_npp[bra];
             const int pk0 = M.pair_ppoff[ket], nkp = M.pair_npp[ket];
-            const F *gam = myG + set * N;
+            const int gbase = (lane_ok ? team : 0) * K::GSTRIDE + set * N;
             for (int ib = 0; ib < nbp; ++ib) {
-                const double p = M.pp_p[pb0 + ib], cab = M.pp_c[pb0 + ib], zb2 = 2.0 * M.pp_zb[pb0 + ib];
+                const double p = M.pp_p[pb0 + ib], ip = M.pp_ip[pb0 + ib], zb2 = 2.0 * M.pp_zb[pb0 + ib];
+                // 2 pi^(5/2) times the bra contraction factor over p
+                const double cab = 34.98683665524972 * M.pp_c[pb0 + ib] * ip;
                 const double P[3] = {M.pp_Px[pb0 + ib], M.pp_Py[pb0 + ib], M.pp_Pz[pb0 + ib]};
                 for (int ik = 0; ik < nkp; ++ik) {
-                    const double q = M.pp_p[pk0 + ik], ccd = M.pp_c[pk0 + ik];
+                    // Gamma is re-read from LDS for every primitive quartet: an opaque offset
+                    // keeps the compiler from hoisting all N values into registers
+                    int goff = gbase;
+                    if constexpr (N > 8) asm volatile("" : "+v"(goff));
+                    const F *gam = s_gam + goff;
+                    const double q = M.pp_p[pk0 + ik], iq = M.pp_ip[pk0 + ik], ccd = M.pp_c[pk0 + ik];
                     const double zc2 = 2.0 * M.pp_za[pk0 + ik], zd2 = 2.0 * M.pp_zb[pk0 + ik];
                     const double Q[3] = {M.pp_Px[pk0 + ik], M.pp_Py[pk0 + ik], M.pp_Pz[pk0 + ik]};
-                    const double ipq = 1.0 / (p + q);
+                    const double sipq = rsq64(p + q), ipq = sipq * sipq;
                     const double rho = p * q * ipq;
                     double PQ[3], pq2 = 0.0;
 #pragma unroll
@@ -321,9 +376,10 @@ k_deriv(const DerivArgs a)
                         PQ[d] = P[d] - Q[d];
                         pq2 += PQ[d] * PQ[d];
                     }
-                    double Tr = rho * pq2, eta = 1.0;
+                    double Tr = rho * pq2, eta = 1.0, seta = 1.0;
                     if (LR && set) {
-                        eta = om2 / (om2 + rho);
+                        seta = rsq64(1.0 + rho * iom2); // sqrt(omega^2 / (omega^2 + rho))
+                        eta = seta * seta;
                         Tr *= eta;
                     }
                     double u, w;
@@ -331,18 +387,18 @@ k_deriv(const DerivArgs a)
                     else rys_root<NR>(Tr, ir, u, w);
                     if (LR && set) {
                         u *= eta;
-                        w *= sqrt(eta);
+                        w *= seta;
                     }
                     // 2 pi^(5/2) / (p q sqrt(p+q)) times contraction and pair factors
-                    const double pref = 34.98683665524972 / (p * q) * sqrt(ipq) * cab * ccd * w;
+                    const double pref = cab * (ccd * iq) * sipq * w;
                     const double B00 = 0.5 * u * ipq;
-                    const double B10 = 0.5 / p * (1.0 - q * ipq * u);
-                    const double B01 = 0.5 / q * (1.0 - p * ipq * u);
+                    const double B10 = 0.5 * ip * (1.0 - q * ipq * u);
+                    const double B01 = 0.5 * iq * (1.0 - p * ipq * u);
                     const double cq = q * ipq * u, cp = p * ipq * u;
                     F pacc[9];
 #pragma unroll
                     for (int k = 0; k < 9; ++k) pacc[k] = F(0);
-                    if constexpr (!DIRECT) {
+                    if constexpr (MODE == 0) {
                         Rys2D<LA + LB + 1, LC + LD + 1, LA, LB + 1, LD + 1, F> g[3];
 #pragma unroll
                         for (int d = 0; d < 3; ++d) {
@@ -378,10 +434,10 @@ k_deriv(const DerivArgs a)
                                         pacc[3] += tyz * dC[0]; pacc[4] += txz * dC[1]; pacc[5] += txy * dC[2];
                                         pacc[6] += tyz * dD[0]; pacc[7] += txz * dD[1]; pacc[8] += txy * dD[2];
                                     }
-                    } else {
+                    } else if constexpr (MODE == 1) {
                         constexpr int NBASE = (LA + 1) * (LB + 1) * (LC + 1) * (LD + 1);
                         const double za = M.pp_za[pb0 + ib];
-                        const DirectCoef dc = direct_coef(za, 0.5 * zb2, 0.5 * zc2, 0.5 * zd2, p, q, u, ipq, B10, B01, B00);
+                        const DirectCoef dc = direct_coef(za, 0.5 * zb2, 0.5 * zc2, 0.5 * zd2, p, q, ip, iq, u, ipq, B10, B01, B00);
                         F T[3][4 * NBASE];
 #pragma unroll
                         for (int d = 0; d < 3; ++d) {
@@ -421,6 +477,53 @@ k_deriv(const DerivArgs a)
                                 if constexpr (FLUSH == 2) flush(acc, pacc);
                             }
                             if constexpr (FLUSH == 1) flush(acc, pacc);
+                        }
+                    } else {
+                        constexpr int NBASE = (LA + 1) * (LB + 1) * (LC + 1) * (LD + 1);
+                        const double za = M.pp_za[pb0 + ib];
+                        const DirectCoef dc = direct_coef(za, 0.5 * zb2, 0.5 * zc2, 0.5 * zd2, p, q, ip, iq, u, ipq, B10, B01, B00);
+                        F I[3][NBASE], H[3][NBASE];
+                        double CB[3], CCx[3], CDx[3];
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const double CA = (P[d] - A[d]) - cq * PQ[d];
+                            CB[d] = CA + AB[d];
+                            CCx[d] = (Q[d] - Cc[d]) + cp * PQ[d];
+                            CDx[d] = CCx[d] + CD[d];
+                            direct_base<LA, LB, LC, LD, F>(I[d], F(d == 2 ? pref : 1.0), F(CA), F(CB[d]), F(CCx[d]),
+                                                           F(CDx[d]), F(B10), F(B01), F(B00));
+#pragma unroll
+                            for (int e = 0; e < NBASE; ++e) H[d][e] = F(0);
+                        }
+#pragma unroll
+                        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                            for (int ib2 = 0; ib2 < NB; ++ib2)
+#pragma unroll
+                                for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                                    for (int id = 0; id < ND; ++id) {
+                                        const int c = ((ia * NB + ib2) * NC + ic) * ND + id;
+                                        const F gm = gam[c];
+                                        int e[3];
+#pragma unroll
+                                        for (int d = 0; d < 3; ++d)
+                                            e[d] = ((kCart.v[LA][ia][d] * (LB + 1) + kCart.v[LB][ib2][d]) * (LC + 1) +
+                                                    kCart.v[LC][ic][d]) * (LD + 1) + kCart.v[LD][id][d];
+                                        const F vx = I[0][e[0]], vy = I[1][e[1]], vz = I[2][e[2]];
+                                        const F gz = gm * vz;
+                                        H[0][e[0]] += gz * vy;
+                                        H[1][e[1]] += gz * vx;
+                                        H[2][e[2]] += (gm * vx) * vy;
+                                    }
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            double S[5];
+                            collapse_sums<LA, LB, LC, LD, F>(H[d], I[d], S);
+                            const double sij = S[1] + S[2], skl = S[3] + S[4];
+                            acc[d] += zb2 * CB[d] * S[0] + dc.e2 * S[1] + dc.e3 * S[2] + dc.e4 * skl;
+                            acc[3 + d] += zc2 * CCx[d] * S[0] + dc.f2 * S[3] + dc.f3 * S[4] + dc.f4 * sij;
+                            acc[6 + d] += zd2 * CDx[d] * S[0] + dc.g2 * S[3] + dc.g3 * S[4] + dc.g4 * sij;
                         }
                     }
 #pragma unroll

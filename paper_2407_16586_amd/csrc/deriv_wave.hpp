@@ -146,7 +146,7 @@ k_deriv_wave(const DerivArgs a)
             eoff[q][d] = d * 4 * NBASE + ((i * (LB + 1) + j) * (LC + 1) + k) * (LD + 1) + l;
         }
     }
-    const double om2 = a.omega * a.omega;
+    const double iom2 = LR ? 1.0 / (a.omega * a.omega) : 0.0;
     const long long wstride = (long long)gridDim.x * K::WAVES;
     for (long long t = (long long)blockIdx.x * K::WAVES + wave; t < a.ntasks; t += wstride) {
         const DerivArgs &M = a.batch ? a.batch[a.task_mol[t]] : a;
@@ -188,30 +188,32 @@ k_deriv_wave(const DerivArgs a)
                 for (int ch = 0; ch < NCHUNK; ++ch) {
                     const int slot = ch * CH + s1;
                     if (s1 < CH && slot < NSLOT) {
-                        const double p = M.pp_p[pb0 + ib], cab = M.pp_c[pb0 + ib], zb2 = 2.0 * M.pp_zb[pb0 + ib];
-                        const double q = M.pp_p[pk0 + ik], ccd = M.pp_c[pk0 + ik];
+                        const double p = M.pp_p[pb0 + ib], ip = M.pp_ip[pb0 + ib], cab = M.pp_c[pb0 + ib];
+                        const double zb2 = 2.0 * M.pp_zb[pb0 + ib];
+                        const double q = M.pp_p[pk0 + ik], iq = M.pp_ip[pk0 + ik], ccd = M.pp_c[pk0 + ik];
                         const double zc2 = 2.0 * M.pp_za[pk0 + ik], zd2 = 2.0 * M.pp_zb[pk0 + ik];
                         const double P[3] = {M.pp_Px[pb0 + ib], M.pp_Py[pb0 + ib], M.pp_Pz[pb0 + ib]};
                         const double Q[3] = {M.pp_Px[pk0 + ik], M.pp_Py[pk0 + ik], M.pp_Pz[pk0 + ik]};
-                        const double ipq = 1.0 / (p + q), rho = p * q * ipq;
+                        const double sipq = rsq64(p + q), ipq = sipq * sipq, rho = p * q * ipq;
                         const double PQ0 = P[0] - Q[0], PQ1 = P[1] - Q[1], PQ2 = P[2] - Q[2];
                         const double pq2 = PQ0 * PQ0 + PQ1 * PQ1 + PQ2 * PQ2;
                         const int set = slot / NR, ir = slot % NR;
-                        double Tr = rho * pq2, eta = 1.0;
+                        double Tr = rho * pq2, eta = 1.0, seta = 1.0;
                         if (LR && set) {
-                            eta = om2 / (om2 + rho);
+                            seta = rsq64(1.0 + rho * iom2); // sqrt(omega^2 / (omega^2 + rho))
+                            eta = seta * seta;
                             Tr *= eta;
                         }
                         double u, w;
                         rys_root<NR>(Tr, ir, u, w);
                         if (LR && set) {
                             u *= eta;
-                            w *= sqrt(eta);
+                            w *= seta;
                         }
-                        const double pref = 34.98683665524972 / (p * q) * sqrt(ipq) * cab * ccd * w;
+                        const double pref = 34.98683665524972 * (cab * ip) * (ccd * iq) * sipq * w;
                         const double B00 = 0.5 * u * ipq;
-                        const double B10 = 0.5 / p * (1.0 - q * ipq * u);
-                        const double B01 = 0.5 / q * (1.0 - p * ipq * u);
+                        const double B10 = 0.5 * ip * (1.0 - q * ipq * u);
+                        const double B01 = 0.5 * iq * (1.0 - p * ipq * u);
                         const double PQd = d1 == 0 ? PQ0 : (d1 == 1 ? PQ1 : PQ2);
                         const double Pd = P[d1 == 0 ? 0 : (d1 == 1 ? 1 : 2)], Qd = Q[d1 == 0 ? 0 : (d1 == 1 ? 1 : 2)];
                         if constexpr (sizeof(F) == sizeof(double)) {
@@ -222,7 +224,7 @@ k_deriv_wave(const DerivArgs a)
                         } else {
                             const double za = M.pp_za[pb0 + ib];
                             const DirectCoef dc =
-                                direct_coef(za, 0.5 * zb2, 0.5 * zc2, 0.5 * zd2, p, q, u, ipq, B10, B01, B00);
+                                direct_coef(za, 0.5 * zb2, 0.5 * zc2, 0.5 * zd2, p, q, ip, iq, u, ipq, B10, B01, B00);
                             const double CA = (Pd - Ad) - q * ipq * u * PQd, CB = CA + ABd;
                             const double CCx = (Qd - Cd) + p * ipq * u * PQd, CDx = CCx + CDd;
                             F *o = tab + s1 * TAB + d1 * 4 * NBASE;

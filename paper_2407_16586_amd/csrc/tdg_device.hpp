@@ -45,6 +45,27 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// 1/x and 1/sqrt(x) for positive normal x: the hardware estimate refined by two
+// Newton steps (each squares the relative error), cheaper than the IEEE division
+// and square-root sequences
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+__device__ __forceinline__ double rsq64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double h = 0.5 * y, g = x * y;
+        y = fma(y, fma(-g, h, 0.5), y);
+    }
+    return y;
+}
+
 // ------------------------------------------------------------------ Rys rule
 template <int N> __device__ __forceinline__ const double *rys_poly();
 template <> __device__ __forceinline__ const double *rys_poly<1>() { return rys_poly_1; }
@@ -84,10 +105,10 @@ __device__ __forceinline__ void rys_root(double T, int r, double &u, double &w)
         u = a;
         w = b;
     } else {
-        const double it = 1.0 / T;
-        const double xh = rys_hx<N>()[r];
-        u = xh * xh * it;
-        w = rys_hw<N>()[r] * sqrt(it);
+        const double st = rsq64(T);
+        const double xh = rys_hx<N>()[r] * st;
+        u = xh * xh;
+        w = rys_hw<N>()[r] * st;
     }
 }
 
@@ -119,10 +140,10 @@ __device__ __forceinline__ void rys_root_lds(const double *tab, double T, int r,
         u = a;
         w = b;
     } else {
-        const double it = 1.0 / T;
-        const double xh = rys_hx<N>()[r];
-        u = xh * xh * it;
-        w = rys_hw<N>()[r] * sqrt(it);
+        const double st = rsq64(T);
+        const double xh = rys_hx<N>()[r] * st;
+        u = xh * xh;
+        w = rys_hw<N>()[r] * st;
     }
 }
 

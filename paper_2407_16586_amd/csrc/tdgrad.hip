@@ -125,7 +125,7 @@ struct tdg_plan {
     DevBuf<int> d_shell_atom, d_shell_ao, d_shell_l;
     DevBuf<int> d_pair_sa, d_pair_sb, d_pair_ppoff, d_pair_npp, d_pair_K;
     DevBuf<double> d_pair_Q;
-    DevBuf<double> d_pp_p, d_pp_Px, d_pp_Py, d_pp_Pz, d_pp_c, d_pp_za, d_pp_zb;
+    DevBuf<double> d_pp_p, d_pp_Px, d_pp_Py, d_pp_Pz, d_pp_c, d_pp_za, d_pp_zb, d_pp_ip;
     DevBuf<double> d_ang;                  // angular normalisation per AO
     DevBuf<int> d_grp_start;
     // work buffers
@@ -143,6 +143,8 @@ struct tdg_plan {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ev_cls[kNumClasses + 1] = {};
     int variant[2][kNumClasses];           // kernel variant per (precision, class): 0 team, 1 wavefront, 2 direct team
+    bool v0_ok[2][kNumClasses];            // variant 0 offered: its kernel keeps its tables in registers
+                                           // (no scratch memory); otherwise variant 2 runs in its place
     int split[kNumClasses];                // 1: the FP32-routed quartets of the class run in FP32; 0: the
                                            // whole class runs in FP64 (measured faster by the autotuner)
     std::vector<double> pair_pmax;         // largest primitive exponent sum of each sorted pair
@@ -580,6 +582,12 @@ static const LaunchFn kLaunch[kNumClasses] = {
     tdg_launch_class_10, tdg_launch_class_11, tdg_launch_class_12, tdg_launch_class_13, tdg_launch_class_14,
     tdg_launch_class_15, tdg_launch_class_16, tdg_launch_class_17, tdg_launch_class_18, tdg_launch_class_19,
     tdg_launch_class_20};
+static const ScratchFn kScratch[kNumClasses] = {
+    tdg_class_scratch_0,  tdg_class_scratch_1,  tdg_class_scratch_2,  tdg_class_scratch_3,  tdg_class_scratch_4,
+    tdg_class_scratch_5,  tdg_class_scratch_6,  tdg_class_scratch_7,  tdg_class_scratch_8,  tdg_class_scratch_9,
+    tdg_class_scratch_10, tdg_class_scratch_11, tdg_class_scratch_12, tdg_class_scratch_13, tdg_class_scratch_14,
+    tdg_class_scratch_15, tdg_class_scratch_16, tdg_class_scratch_17, tdg_class_scratch_18, tdg_class_scratch_19,
+    tdg_class_scratch_20};
 
 static int class_ncomp(int c)
 {
@@ -645,7 +653,7 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
                         std::vector<double> *pp) {
         off.resize(v.size());
         cnt.resize(v.size());
-        for (int k = 0; k < 7; ++k) pp[k].clear();
+        for (int k = 0; k < 8; ++k) pp[k].clear();
         for (size_t i = 0; i < v.size(); ++i) {
             const int sa = v[i].sa, sb = v[i].sb;
             const double *A = b->coords + 3 * b->shell_atom[sa], *B = b->coords + 3 * b->shell_atom[sb];
@@ -662,14 +670,17 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
                     pp[4].push_back(c);
                     pp[5].push_back(za);
                     pp[6].push_back(zb);
+                    pp[7].push_back(1.0 / p);
                 }
             cnt[i] = (int)pp[0].size() - off[i];
         }
     };
     std::vector<int> off, cnt;
-    std::vector<double> pp[7];
+    std::vector<double> pp[8];
     build_pp(pr, off, cnt, pp);
     if (pp[0].size() > (size_t)0x7fffffff) return fail(TDG_EUNSUPPORTED, "too many primitive pairs");
+    for (const auto &v : pp)
+        if (v.size() != pp[0].size()) return fail(TDG_EINVAL, "internal: primitive-pair tables of unequal length");
 
     int rc;
     std::vector<int> sa(np), sb(np);
@@ -793,7 +804,7 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
         (rc = pl->d_pair_Q.upload(pl->pair_Q)) || (rc = pl->d_grp_start.upload(pl->grp_start)) ||
         (rc = pl->d_pp_p.upload(pp[0])) || (rc = pl->d_pp_Px.upload(pp[1])) || (rc = pl->d_pp_Py.upload(pp[2])) ||
         (rc = pl->d_pp_Pz.upload(pp[3])) || (rc = pl->d_pp_c.upload(pp[4])) || (rc = pl->d_pp_za.upload(pp[5])) ||
-        (rc = pl->d_pp_zb.upload(pp[6])))
+        (rc = pl->d_pp_zb.upload(pp[6])) || (rc = pl->d_pp_ip.upload(pp[7])))
         return rc;
     // screening items: (class, bra pair)
     pl->item_class_off.assign(kNumClasses + 1, 0);
@@ -814,10 +825,14 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
     HIP_TRY(hipEventCreate(&pl->ev0));
     HIP_TRY(hipEventCreate(&pl->ev1));
     for (auto &e : pl->ev_cls) HIP_TRY(hipEventCreate(&e));
+    const bool lr = (pl->prm.terms & 4) && pl->prm.beta != 0.0;
     for (int pr = 0; pr < 2; ++pr)
-        for (int c = 0; c < kNumClasses; ++c)
-            pl->variant[pr][c] = pl->bvariant[pr][c] =
-                pl->prm.kernel_variant >= 0 ? pl->prm.kernel_variant : default_variant(c);
+        for (int c = 0; c < kNumClasses; ++c) {
+            pl->v0_ok[pr][c] = kScratch[c](0, pr, lr) == 0;
+            int v = pl->prm.kernel_variant >= 0 ? pl->prm.kernel_variant : default_variant(c);
+            if (v == 0 && !pl->v0_ok[pr][c]) v = 2;
+            pl->variant[pr][c] = pl->bvariant[pr][c] = v;
+        }
     for (int c = 0; c < kNumClasses; ++c) pl->split[c] = pl->bsplit[c] = 1;
     HIP_TRY(hipDeviceSynchronize());
     return TDG_OK;
@@ -882,7 +897,7 @@ int tdg_plan_destroy(tdg_plan_t *pl)
     if (!pl) return TDG_OK;
     hipSetDevice(pl->device);
     DevBuf<double> *dbl[] = {&pl->d_coords, &pl->d_pair_Q, &pl->d_pp_p, &pl->d_pp_Px, &pl->d_pp_Py, &pl->d_pp_Pz,
-                             &pl->d_pp_c, &pl->d_pp_za, &pl->d_pp_zb, &pl->d_ang, &pl->d_in, &pl->d_Pn, &pl->d_Dn,
+                             &pl->d_pp_c, &pl->d_pp_za, &pl->d_pp_zb, &pl->d_pp_ip, &pl->d_ang, &pl->d_in, &pl->d_Pn, &pl->d_Dn,
                              &pl->d_Rn, &pl->d_mP, &pl->d_mD, &pl->d_mR, &pl->d_grad};
     for (auto *x : dbl) x->release();
     DevBuf<int> *ints[] = {&pl->d_shell_atom, &pl->d_shell_ao, &pl->d_shell_l, &pl->d_pair_sa, &pl->d_pair_sb,
@@ -1092,7 +1107,7 @@ static DerivArgs deriv_args(tdg_plan *pl)
     a.pair_sa = pl->d_pair_sa.p; a.pair_sb = pl->d_pair_sb.p; a.pair_ppoff = pl->d_pair_ppoff.p;
     a.pair_npp = pl->d_pair_npp.p;
     a.pp_p = pl->d_pp_p.p; a.pp_Px = pl->d_pp_Px.p; a.pp_Py = pl->d_pp_Py.p; a.pp_Pz = pl->d_pp_Pz.p;
-    a.pp_c = pl->d_pp_c.p; a.pp_za = pl->d_pp_za.p; a.pp_zb = pl->d_pp_zb.p;
+    a.pp_c = pl->d_pp_c.p; a.pp_za = pl->d_pp_za.p; a.pp_zb = pl->d_pp_zb.p; a.pp_ip = pl->d_pp_ip.p;
     a.Pn = pl->d_Pn.p; a.Dn = pl->d_Dn.p; a.Rn = pl->d_Rn.p; a.n_bf = pl->n_bf;
     a.omega = pl->prm.omega; a.alpha = pl->prm.alpha; a.beta = pl->prm.beta; a.terms = pl->prm.terms;
     a.grad = pl->d_grad.p; a.n_atoms = pl->n_atoms;
@@ -1240,7 +1255,8 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
         if (lead->prm.autotune && lead->prm.kernel_variant < 0 && !tuned) {
             // a12 autotuner: time the kernel variants of each class on this call's task list
             // (into scratch gradients) and keep the fastest for later calls.  The wavefront
-            // design is a candidate for classes with >= 27 components.  With the mixed route
+            // design is a candidate for classes with >= 27 components, the two team designs
+            // for every class.  With the mixed route
             // it also decides the precision per class: the FP32-routed quartets run in FP32
             // only where FP64 over the whole class measures slower.
             std::vector<DerivArgs> targs;
@@ -1269,8 +1285,9 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                 at.task_mol = task_mol ? task_mol + b : nullptr;
                 at.ntasks = e - b;
                 best = 1e30f;
-                for (int v = 0; v < 2; ++v) {
+                for (int v = 0; v < 3; ++v) {
                     if (v == 1 && class_ncomp(c) < 27) continue;
+                    if (v == 0 && !lead->v0_ok[pr][c]) continue;
                     float ms = 0.f;
                     for (int rep = 0; rep < 2; ++rep) { // the second launch is the measured one
                         HIP_TRY(hipEventRecord(lead->ev_cls[0], st));

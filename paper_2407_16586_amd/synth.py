@@ -10,11 +10,15 @@ Shapes follow the paper's workload class (section III.A): protein-like
 first-row/hydrogen systems with a contracted core s shell, split valence and
 one d polarisation shell on heavy atoms, Cartesian functions, l <= 2.
 
-Basis recipe per atom (exponents log-uniform in [0.1, 5000], sorted
-descending within each shell; contraction coefficients N(0,1), normalised by
-the consumer):
-  heavy : s(6) s(1) s(1) p(3) p(1) d(1)   -> 6 shells, 13 prims, 15 functions
-  H     : s(3) s(1) p(1)                  -> 3 shells,  5 prims,  5 functions
+Basis recipe per atom, shaped like the def2-SVP basis of the paper's runs
+(section III.A): a segmented [3s2p1d] / [2s1p] contraction with exponents drawn
+log-uniformly from a range per shell (sorted descending within a shell) and
+positive contraction coefficients exp(N(0, 0.5)), normalised by the consumer:
+  heavy : s(6) [3, 5000]  s(1) [0.3, 1.0]  s(1) [0.08, 0.3]
+          p(3) [0.4, 15]  p(1) [0.1, 0.3]  d(1) [0.4, 1.5]
+          -> 6 shells, 13 prims, 15 Cartesian functions
+  H     : s(3) [0.4, 15]  s(1) [0.1, 0.25] p(1) [0.6, 1.2]
+          -> 3 shells,  5 prims,  5 functions
 
 Densities (definitions of section II.A): P0 = occ * C_o C_o^T,
 R = C_o X C_v^T with X an n_occ x n_vir amplitude matrix of unit Frobenius
@@ -31,9 +35,10 @@ import numpy as np
 
 BASE_SEED = 20240716
 
-HEAVY_RECIPE = ((0, 6), (0, 1), (0, 1), (1, 3), (1, 1), (2, 1))
-H_RECIPE = ((0, 3), (0, 1), (1, 1))
-EXP_RANGE = (0.1, 5000.0)
+# (l, primitives, exponent range) per shell
+HEAVY_RECIPE = ((0, 6, (3.0, 5000.0)), (0, 1, (0.3, 1.0)), (0, 1, (0.08, 0.3)),
+                (1, 3, (0.4, 15.0)), (1, 1, (0.1, 0.3)), (2, 1, (0.4, 1.5)))
+H_RECIPE = ((0, 3, (0.4, 15.0)), (0, 1, (0.1, 0.25)), (1, 1, (0.6, 1.2)))
 
 # range-separated hybrid parameters of the paper's production functional
 OMEGA = 0.3
@@ -100,15 +105,14 @@ class Molecule:
 
 
 def _build_basis(rng: np.random.Generator, Z: np.ndarray):
-    lo, hi = math.log(EXP_RANGE[0]), math.log(EXP_RANGE[1])
     sh_atom, sh_l, sh_np, sh_po, sh_ao = [], [], [], [], []
     exps, coefs = [], []
     ao = 0
     for ia, z in enumerate(Z):
         recipe = H_RECIPE if z == 1 else HEAVY_RECIPE
-        for l, k in recipe:
-            e = np.sort(np.exp(rng.uniform(lo, hi, size=k)))[::-1]
-            c = rng.standard_normal(k)
+        for l, k, (elo, ehi) in recipe:
+            e = np.sort(np.exp(rng.uniform(math.log(elo), math.log(ehi), size=k)))[::-1]
+            c = np.exp(0.5 * rng.standard_normal(k))
             sh_atom.append(ia)
             sh_l.append(l)
             sh_np.append(k)

@@ -147,7 +147,7 @@ def test_device_pointer_path(tdg, oracle_lib, mol0):
     assert np.abs(out.cpu().numpy() - ref).max() <= TOL
 
 
-@pytest.mark.parametrize("variant", [-1, 1])
+@pytest.mark.parametrize("variant", [-1, 0, 1, 2])
 def test_chain60_against_stored_oracle(tdg, variant):
     """Full 60-atom, 500-function chain at the production threshold 1e-10 against the
     oracle's gradient stored by tests/golden/make_golden.py."""
@@ -172,7 +172,11 @@ def test_both_kernel_variants_all_classes(tdg, oracle_lib, mol0, variant):
     for m in (mol0, molecules.small_mixed()):
         p = tdg.Plan(m, schwarz_tol=0.0, kernel_variant=variant)
         g, st = p.grad(m.P0, m.PD, m.R, stats=True)
-        assert all((v & 3) == variant for v, n in zip(st["class_variant"], st["class_quartets"]) if n)
+        # variant 0 is replaced by 2 on classes whose variant-0 kernel would need scratch memory
+        assert all((v & 3) == variant or (variant == 0 and (v & 3) == 2)
+                   for v, n in zip(st["class_variant"], st["class_quartets"]) if n)
+        if variant == 0:
+            assert any((v & 3) == 0 for v, n in zip(st["class_variant"], st["class_quartets"]) if n)
         ref = oracle_lib.grad(m)
         err = np.abs(g - ref).max()
         _say("  max-abs", err)
@@ -196,7 +200,7 @@ def test_autotuned_plan_is_stable(tdg, mol0, oracle_lib):
 MIXED_TOL = 1e-6
 
 
-@pytest.mark.parametrize("variant", [-1, 0, 1])
+@pytest.mark.parametrize("variant", [-1, 0, 1, 2])
 def test_mixed_precision_small(tdg, oracle_lib, mol0, variant):
     """FP32 2D integrals (FP64 roots, prefactors, sums) within 1e-6 of the FP64 oracle,
     with every quartet routed to FP32 (thresholds at infinity) and with the defaults."""
