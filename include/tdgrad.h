@@ -102,9 +102,11 @@ typedef struct {
                                kernels (FP64: vertical recursion + transfers; FP32: direct
                                four-centre derivative tables); 1: wavefront-per-quartet kernels;
                                2: team-per-quartet kernels with direct four-centre base tables
-                               and the collapsed contraction.  Variant 0 is offered only for
-                               classes whose variant-0 kernel needs no scratch memory; there
-                               variant 2 runs instead (stats report the variant that ran) */
+                               and the collapsed contraction; 3, 4: as 0, 2 with one lane per
+                               (quartet, range) looping over the Rys roots, for classes with
+                               <= 27 components (elsewhere 0, 2 run).  The transfer form (0, 3)
+                               is offered only where its kernel needs no scratch memory; there
+                               2 (4) runs instead.  Stats report the variant that ran. */
     double mixed_tau64; /* mixed mode: FP32 only when bound * f_ab * f_cd is below this */
     double mixed_p64;   /* mixed mode: pairs with a primitive exponent sum >= this stay FP64 */
     int64_t max_tasks;  /* screened quartets held at once (chunking of large systems); 0 = 2^31 */
@@ -118,9 +120,9 @@ typedef struct {
     int64_t class_quartets[21];/* per angular class, in the library's class order */
     int64_t class_prim_quartets[21];
     double class_ms[21];       /* derivative-kernel time per class (HIP events on the call's stream) */
-    int32_t class_variant[21]; /* kernel variant per class: bits 0-1 the FP64 list's, bits 2-3 the
-                                  FP32 list's (0 team, 1 wavefront, 2 collapsed team);
-                                  bit 4 set: the FP32-routed quartets ran in FP64 */
+    int32_t class_variant[21]; /* kernel variant per class (kernel_variant numbering): bits 0-2
+                                  the FP64 list's, bits 3-5 the FP32 list's; bit 6 set: the
+                                  FP32-routed quartets ran in FP64 */
     int64_t fp32_quartets;     /* mixed mode: quartets evaluated with FP32 2D integrals (those
                                   routed to FP32 in classes that run the FP32 kernels) */
     int64_t ml_skipped;        /* quartets vetoed by the contribution estimator */

@@ -28,48 +28,97 @@ constexpr int class_pk(int c)
 }
 constexpr int LA = kPL[class_pb(TDG_CLASS)][0], LB = kPL[class_pb(TDG_CLASS)][1];
 constexpr int LC = kPL[class_pk(TDG_CLASS)][0], LD = kPL[class_pk(TDG_CLASS)][1];
+// the per-range team layout (variants 3, 4) exists for classes with <= 27 components
+constexpr bool kAllRoots = (LA + 1) * (LA + 2) / 2 * ((LB + 1) * (LB + 2) / 2) * ((LC + 1) * (LC + 2) / 2) *
+                               ((LD + 1) * (LD + 2) / 2) <= 27;
 
-template <bool LR, typename F>
+template <bool LR, typename F, bool BATCH>
 hipError_t go(int variant, const tdg::DerivArgs &a, hipStream_t st, int grid_max)
 {
     using namespace tdg;
     const size_t dyn = a.lds_atoms ? (size_t)3 * a.n_atoms * sizeof(double) : 0;
+    if constexpr (kAllRoots) {
+        if (variant == 3 || variant == 4) {
+            using K = DerivClass<LA, LB, LC, LD, LR, F, true>;
+            const long long blocks = (a.ntasks + K::TPB - 1) / K::TPB;
+            const int grid = (int)(blocks < grid_max ? blocks : grid_max);
+            if (variant == 4)
+                hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 2, BATCH, true>), dim3(grid), dim3(K::BLOCK), dyn,
+                                   st, a);
+            else if constexpr (sizeof(F) != sizeof(double))
+                hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 1, BATCH, true>), dim3(grid), dim3(K::BLOCK), dyn,
+                                   st, a);
+            else
+                hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 0, BATCH, true>), dim3(grid), dim3(K::BLOCK), dyn,
+                                   st, a);
+            return hipGetLastError();
+        }
+    }
+    if (variant == 3) variant = 0; // classes without the per-range layout
+    if (variant == 4) variant = 2;
     if (variant == 0 || variant == 2) {
         using K = DerivClass<LA, LB, LC, LD, LR, F>;
         const long long blocks = (a.ntasks + K::TPB - 1) / K::TPB;
         const int grid = (int)(blocks < grid_max ? blocks : grid_max);
         if (variant == 2)
-            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 2>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 2, BATCH>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
         else if constexpr (sizeof(F) != sizeof(double))
-            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 1>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 1, BATCH>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
         else
-            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 0>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 0, BATCH>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
     } else {
         using K = WaveClass<LA, LB, LC, LD, LR, F>;
         const long long blocks = (a.ntasks + K::WAVES - 1) / K::WAVES;
         const int grid = (int)(blocks < grid_max ? blocks : grid_max);
-        hipLaunchKernelGGL((k_deriv_wave<LA, LB, LC, LD, LR, F>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+        hipLaunchKernelGGL((k_deriv_wave<LA, LB, LC, LD, LR, F, BATCH>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
     }
     return hipGetLastError();
 }
+
 template <bool LR, typename F>
+hipError_t go(int variant, const tdg::DerivArgs &a, hipStream_t st, int grid_max)
+{
+    return a.batch ? go<LR, F, true>(variant, a, st, grid_max) : go<LR, F, false>(variant, a, st, grid_max);
+}
+
+template <bool LR, typename F, bool BATCH>
 const void *kernel_ptr(int variant)
 {
     using namespace tdg;
-    if (variant == 1) return reinterpret_cast<const void *>(&k_deriv_wave<LA, LB, LC, LD, LR, F>);
-    if (variant == 2) return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 2>);
-    if constexpr (sizeof(F) != sizeof(double)) return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 1>);
-    else return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 0>);
+    if constexpr (kAllRoots) {
+        if (variant == 4) return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 2, BATCH, true>);
+        if (variant == 3) {
+            if constexpr (sizeof(F) != sizeof(double))
+                return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 1, BATCH, true>);
+            else
+                return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 0, BATCH, true>);
+        }
+    }
+    if (variant == 3) variant = 0;
+    if (variant == 4) variant = 2;
+    if (variant == 1) return reinterpret_cast<const void *>(&k_deriv_wave<LA, LB, LC, LD, LR, F, BATCH>);
+    if (variant == 2) return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 2, BATCH>);
+    if constexpr (sizeof(F) != sizeof(double))
+        return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 1, BATCH>);
+    else
+        return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 0, BATCH>);
+}
+
+template <bool LR, typename F>
+size_t scratch_of(int variant)
+{
+    hipFuncAttributes a1{}, a2{};
+    if (hipFuncGetAttributes(&a1, kernel_ptr<LR, F, false>(variant)) != hipSuccess ||
+        hipFuncGetAttributes(&a2, kernel_ptr<LR, F, true>(variant)) != hipSuccess)
+        return (size_t)-1;
+    return a1.localSizeBytes > a2.localSizeBytes ? a1.localSizeBytes : a2.localSizeBytes;
 }
 } // namespace
 
 size_t TDG_SCRATCH_NAME(TDG_CLASS)(int variant, int prec, bool lr)
 {
-    const void *fn = prec ? (lr ? kernel_ptr<true, float>(variant) : kernel_ptr<false, float>(variant))
-                          : (lr ? kernel_ptr<true, double>(variant) : kernel_ptr<false, double>(variant));
-    hipFuncAttributes attr{};
-    if (hipFuncGetAttributes(&attr, fn) != hipSuccess) return (size_t)-1;
-    return attr.localSizeBytes;
+    return prec ? (lr ? scratch_of<true, float>(variant) : scratch_of<false, float>(variant))
+                : (lr ? scratch_of<true, double>(variant) : scratch_of<false, double>(variant));
 }
 
 hipError_t TDG_LAUNCH_NAME(TDG_CLASS)(int variant, int prec, const tdg::DerivArgs &a, bool lr, hipStream_t st,

@@ -9,6 +9,8 @@ struct DerivArgs;
 // variant 0: team of lanes per shell quartet (FP64: vertical recursion + transfers;
 // FP32: direct four-centre derivative tables), 1: wavefront per shell quartet,
 // 2: team of lanes with direct four-centre base tables and the collapsed contraction;
+// 3, 4: as 0, 2 with one lane per (quartet, range) looping over the roots (classes with
+// <= 27 components; elsewhere they run as 0, 2);
 // prec 0: FP64 2D integrals, 1: FP32 2D integrals (FP64 roots and sums)
 using LaunchFn = hipError_t (*)(int variant, int prec, const DerivArgs &a, bool lr, hipStream_t st, int grid_max);
 // per-lane scratch (private segment) bytes of a variant's kernel; (size_t)-1 if unknown

@@ -229,12 +229,16 @@ __device__ __forceinline__ void collapse_sums(const F *H, const F *I, double S[5
     S[0] = double(s0); S[1] = double(si); S[2] = double(sj); S[3] = double(sk); S[4] = double(sl);
 }
 
-template <int LA, int LB, int LC, int LD, bool LR, typename F = double>
+// Team layout of the team kernels.  ALLR = false: one lane per (root, range) of a
+// quartet; ALLR = true: one lane per range, looping over the roots (the primitive-pair
+// setup is then done once per range instead of once per root).
+template <int LA, int LB, int LC, int LD, bool LR, typename F = double, bool ALLR = false>
 struct DerivClass {
     static constexpr int L = LA + LB + LC + LD;
     static constexpr int NR = nroots_deriv(L);
     static constexpr int NSET = LR ? 2 : 1;
-    static constexpr int TEAM = NR * NSET;
+    static constexpr int RPL = ALLR ? NR : 1;      // roots per lane
+    static constexpr int TEAM = (NR / RPL) * NSET;
     static constexpr int TPW = kWave / TEAM;
     static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     static constexpr int N = NA * NB * NC * ND;
@@ -275,13 +279,16 @@ __device__ __forceinline__ void gamma_sym(const DerivArgs &a, int mu, int nu, in
 // (double, or float for the mixed-precision route); roots, weights, prefactors and
 // the running sums are FP64 in both.  MODE 0: vertical recursion plus transfers
 // (FP64 only); 1: derivative tables from the direct four-centre recurrence; 2: the
-// direct base tables with the collapsed contraction (collapse_sums).
-template <int LA, int LB, int LC, int LD, bool LR, typename F, int MODE>
-__global__ void __launch_bounds__((DerivClass<LA, LB, LC, LD, LR, F>::BLOCK))
+// direct base tables with the collapsed contraction (collapse_sums).  BATCH: tasks of
+// many molecules, each with its own argument block (a.batch[a.task_mol[t]]); without it
+// every table pointer comes from the kernel arguments.  ALLR: each lane evaluates all
+// roots of its range (see DerivClass).
+template <int LA, int LB, int LC, int LD, bool LR, typename F, int MODE, bool BATCH, bool ALLR = false>
+__global__ void __launch_bounds__((DerivClass<LA, LB, LC, LD, LR, F, ALLR>::BLOCK))
 k_deriv(const DerivArgs a)
 {
-    using K = DerivClass<LA, LB, LC, LD, LR, F>;
-    constexpr int NR = K::NR, TEAM = K::TEAM, TPW = K::TPW, TPB = K::TPB;
+    using K = DerivClass<LA, LB, LC, LD, LR, F, ALLR>;
+    constexpr int NR = K::NR, TEAM = K::TEAM, TPW = K::TPW, TPB = K::TPB, RPL = K::RPL;
     constexpr int NA = K::NA, NB = K::NB, NC = K::NC, ND = K::ND, N = K::N;
     // FP32 route: the per-primitive partial sums go to the FP64 sums after every
     // (a, b) component pair (2) or every a component (1) when those groups hold
@@ -306,7 +313,7 @@ k_deriv(const DerivArgs a)
     }
     const int team = wave * TPW + tw;
     const bool lane_ok = (tw < TPW) && (team < TPB);
-    const int set = r / NR, ir = r % NR;
+    const int set = r / (NR / RPL), ir0 = r % (NR / RPL);
     F *myG = s_gam + (lane_ok ? team : 0) * K::GSTRIDE;
 
     if (a.lds_atoms) {
@@ -319,7 +326,7 @@ k_deriv(const DerivArgs a)
         const long long t = base + team;
         const bool valid = lane_ok && t < a.ntasks;
         int bra = 0, ket = 0, sa = 0, sb = 0, sc = 0, sd = 0;
-        const DerivArgs &M = (a.batch && valid) ? a.batch[a.task_mol[t]] : a;
+        const DerivArgs &M = BATCH ? a.batch[valid ? a.task_mol[t] : 0] : a;
         if (valid) {
             const int2 tk = a.tasks[t];
             bra = tk.x;
@@ -382,6 +389,9 @@ k_deriv(const DerivArgs a)
                         eta = seta * seta;
                         Tr *= eta;
                     }
+#pragma unroll 1
+                    for (int rr = 0; rr < RPL; ++rr) {
+                    const int ir = RPL == 1 ? ir0 : rr;
                     double u, w;
                     if constexpr (K::TAB_LDS) rys_root_lds<NR>(s_rys, Tr, ir, u, w);
                     else rys_root<NR>(Tr, ir, u, w);
@@ -528,6 +538,7 @@ k_deriv(const DerivArgs a)
                     }
 #pragma unroll
                     for (int k = 0; k < 9; ++k) acc[k] += double(pacc[k]);
+                    } // roots of this lane
                 }
             }
         }

@@ -115,7 +115,7 @@ __device__ __forceinline__ void wave_table(F *out /* [4][NBASE] */, F I0, F C00,
     }
 }
 
-template <int LA, int LB, int LC, int LD, bool LR, typename F>
+template <int LA, int LB, int LC, int LD, bool LR, typename F, bool BATCH>
 __global__ void __launch_bounds__((WaveClass<LA, LB, LC, LD, LR, F>::BLOCK))
 k_deriv_wave(const DerivArgs a)
 {
@@ -149,7 +149,7 @@ k_deriv_wave(const DerivArgs a)
     const double iom2 = LR ? 1.0 / (a.omega * a.omega) : 0.0;
     const long long wstride = (long long)gridDim.x * K::WAVES;
     for (long long t = (long long)blockIdx.x * K::WAVES + wave; t < a.ntasks; t += wstride) {
-        const DerivArgs &M = a.batch ? a.batch[a.task_mol[t]] : a;
+        const DerivArgs &M = BATCH ? a.batch[a.task_mol[t]] : a;
         const int2 tk = a.tasks[t];
         const int bra = tk.x, ket = tk.y;
         const int sa = M.pair_sa[bra], sb = M.pair_sb[bra], sc = M.pair_sa[ket], sd = M.pair_sb[ket];

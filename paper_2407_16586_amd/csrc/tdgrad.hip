@@ -143,8 +143,8 @@ struct tdg_plan {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ev_cls[kNumClasses + 1] = {};
     int variant[2][kNumClasses];           // kernel variant per (precision, class): 0 team, 1 wavefront, 2 direct team
-    bool v0_ok[2][kNumClasses];            // variant 0 offered: its kernel keeps its tables in registers
-                                           // (no scratch memory); otherwise variant 2 runs in its place
+    bool tf_ok[2][2][kNumClasses];         // transfer-form variants (0, 3) offered: their kernel keeps its
+                                           // tables in registers (no scratch memory); else 2 (4) runs
     int split[kNumClasses];                // 1: the FP32-routed quartets of the class run in FP32; 0: the
                                            // whole class runs in FP64 (measured faster by the autotuner)
     std::vector<double> pair_pmax;         // largest primitive exponent sum of each sorted pair
@@ -153,7 +153,7 @@ struct tdg_plan {
     DevBuf<double> d_pair_famp;
     DevBuf<int> d_item_cnt32;              // per (class, bra pair) FP32-routed survivor counts
     DevBuf<long long> d_item_off32;
-    bool tuned = false;                    // variants measured on this plan's first call
+    bool tuned[kNumClasses] = {};          // variants of the class measured (on the first chunk holding it)
     DevBuf<double> d_grad_tune;            // scratch gradient for the tuning launches
     // buffers of batched calls led by this plan (the first plan of tdg_grad_jk_batch)
     DevBuf<int2> d_btasks;
@@ -161,7 +161,7 @@ struct tdg_plan {
     DevBuf<DerivArgs> d_bargs;
     int bvariant[2][kNumClasses];
     int bsplit[kNumClasses];
-    bool btuned = false;
+    bool btuned[kNumClasses] = {};
     // learned screening (a13): estimator and thresholds (log10 of the contribution)
     const tdg_mlp *ml = nullptr;
     double ml_log10 = -1e30, ml_tau_hi = 0.0;
@@ -599,6 +599,7 @@ static int class_ncomp(int c)
 // default variant before measurement: the wave-per-quartet kernel for classes whose
 // per-lane register tables would not fit (N >= 81 Cartesian components)
 static int default_variant(int c) { return class_ncomp(c) >= 81 ? 1 : 0; }
+static constexpr int kNumVariants = 5;
 
 template <int LA, int LB>
 static void launch_schwarz(tdg_plan *pl, int i0, int n, const double *ang_ab, double *Q)
@@ -828,9 +829,12 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
     const bool lr = (pl->prm.terms & 4) && pl->prm.beta != 0.0;
     for (int pr = 0; pr < 2; ++pr)
         for (int c = 0; c < kNumClasses; ++c) {
-            pl->v0_ok[pr][c] = kScratch[c](0, pr, lr) == 0;
+            pl->tf_ok[pr][0][c] = kScratch[c](0, pr, lr) == 0;
+            pl->tf_ok[pr][1][c] = class_ncomp(c) <= 27 && kScratch[c](3, pr, lr) == 0;
             int v = pl->prm.kernel_variant >= 0 ? pl->prm.kernel_variant : default_variant(c);
-            if (v == 0 && !pl->v0_ok[pr][c]) v = 2;
+            if ((v == 3 || v == 4) && class_ncomp(c) > 27) v = v == 3 ? 0 : 2;
+            if (v == 0 && !pl->tf_ok[pr][0][c]) v = 2;
+            if (v == 3 && !pl->tf_ok[pr][1][c]) v = 4;
             pl->variant[pr][c] = pl->bvariant[pr][c] = v;
         }
     for (int c = 0; c < kNumClasses; ++c) pl->split[c] = pl->bsplit[c] = 1;
@@ -873,8 +877,8 @@ int tdg_plan_create(const tdg_basis_t *basis, const tdg_params_t *params, int de
     if (params->precision != 0 && params->precision != 1)
         return fail(TDG_EUNSUPPORTED, "precision mode %d not available", params->precision);
     if ((params->terms & 4) && !(params->omega > 0.0)) return fail(TDG_EINVAL, "long-range term needs omega > 0");
-    if (params->kernel_variant < -1 || params->kernel_variant > 2)
-        return fail(TDG_EINVAL, "kernel_variant must be -1, 0, 1 or 2");
+    if (params->kernel_variant < -1 || params->kernel_variant > 4)
+        return fail(TDG_EINVAL, "kernel_variant must be -1 or 0..4");
     int ndev = 0;
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(TDG_EINVAL, "device %d not present (%d devices)", device, ndev);
@@ -1166,7 +1170,7 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
     const int grid_max = ncu * 8;
     int(*variant)[kNumClasses] = batched ? lead->bvariant : lead->variant;
     int *split = batched ? lead->bsplit : lead->split;
-    bool &tuned = batched ? lead->btuned : lead->tuned;
+    bool *tuned = batched ? lead->btuned : lead->tuned;
     long long tot_quartets = 0, tot_fp32 = 0, ml_skipped = 0;
     long long cls_q[kNumClasses] = {0}, cls_q32[kNumClasses] = {0};
     double cls_ms[kNumClasses] = {0.0}, kern_ms = 0.0;
@@ -1252,7 +1256,10 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             x.task_mol = task_mol ? task_mol + ch.seg_begin[c][pr] : nullptr;
             x.ntasks = ch.seg_end[c][pr] - ch.seg_begin[c][pr];
         };
-        if (lead->prm.autotune && lead->prm.kernel_variant < 0 && !tuned) {
+        bool need_tune = false;
+        for (int c = 0; c < kNumClasses; ++c)
+            need_tune |= !tuned[c] && ch.seg_end[c][1] > ch.seg_begin[c][0];
+        if (lead->prm.autotune && lead->prm.kernel_variant < 0 && need_tune) {
             // a12 autotuner: time the kernel variants of each class on this call's task list
             // (into scratch gradients) and keep the fastest for later calls.  The wavefront
             // design is a candidate for classes with >= 27 components, the two team designs
@@ -1285,9 +1292,11 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                 at.task_mol = task_mol ? task_mol + b : nullptr;
                 at.ntasks = e - b;
                 best = 1e30f;
-                for (int v = 0; v < 3; ++v) {
+                for (int v = 0; v < kNumVariants; ++v) {
                     if (v == 1 && class_ncomp(c) < 27) continue;
-                    if (v == 0 && !lead->v0_ok[pr][c]) continue;
+                    if ((v == 3 || v == 4) && class_ncomp(c) > 27) continue;
+                    if (v == 0 && !lead->tf_ok[pr][0][c]) continue;
+                    if (v == 3 && !lead->tf_ok[pr][1][c]) continue;
                     float ms = 0.f;
                     for (int rep = 0; rep < 2; ++rep) { // the second launch is the measured one
                         HIP_TRY(hipEventRecord(lead->ev_cls[0], st));
@@ -1303,6 +1312,8 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             for (int c = 0; c < kNumClasses; ++c) {
                 const long long b0 = ch.seg_begin[c][0], e0 = ch.seg_end[c][0];
                 const long long b1 = ch.seg_begin[c][1], e1 = ch.seg_end[c][1];
+                if (tuned[c] || e1 <= b0) continue;
+                tuned[c] = true;
                 float t_all = 0.f, t64 = 0.f, t32 = 0.f;
                 int v_all = 0, v64 = 0, v32 = 0;
                 if ((rc = best_of(c, 0, b0, e1, t_all, v_all))) return rc;
@@ -1320,7 +1331,6 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             }
             HIP_TRY(hipStreamSynchronize(st));
             d_targs.release();
-            tuned = true;
         }
         HIP_TRY(hipEventRecord(lead->ev0, st));
         for (int c = 0; c < kNumClasses; ++c) {
@@ -1378,7 +1388,7 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                 stats->candidates += (long long)pls[m]->h_cand[c];
             }
             stats->class_ms[c] = cls_ms[c];
-            stats->class_variant[c] = variant[0][c] | (variant[1][c] << 2) | (split[c] ? 0 : 16);
+            stats->class_variant[c] = variant[0][c] | (variant[1][c] << 3) | (split[c] ? 0 : 64);
         }
         stats->quartets = tot_quartets;
         stats->fp32_quartets = tot_fp32;
