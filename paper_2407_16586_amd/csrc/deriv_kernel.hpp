@@ -13,7 +13,7 @@ struct DerivArgs {
     const int *pair_sa, *pair_sb, *pair_ppoff, *pair_npp; // sorted shell pairs
     const double *pp_p, *pp_Px, *pp_Py, *pp_Pz, *pp_c, *pp_za, *pp_zb; // primitive pairs
     const double *pp_ip;    // 1/p of each primitive pair
-    const double *Pn, *Dn, *Rn; // densities with the angular normalisation folded in
+    const double *dens;     // shell-blocked P, D, R records with the angular normalisation folded in
     int n_bf;
     const int2 *tasks;      // (bra pair, ket pair) of this class
     long long ntasks;
@@ -256,23 +256,52 @@ struct DerivClass {
     static constexpr int BLOCK = WAVES * kWave;
 };
 
-__device__ __forceinline__ void gamma_sym(const DerivArgs &a, int mu, int nu, int lam, int sig, double deg,
-                                          double &gf, double &gl)
+// Shell-blocked densities: the record of the ordered shell pair (x, y) starts at
+// 3 (ao_x n_bf + ncart(l_x) ao_y) and holds the P, D and R blocks (ncart(l_x) x ncart(l_y),
+// row-major) back to back, so that every block a quartet reads is contiguous.
+__device__ __forceinline__ size_t dens_rec(int n_bf, int ao_x, int nx, int ao_y)
 {
-    const size_t n = a.n_bf;
-    const double *P = a.Pn, *D = a.Dn, *R = a.Rn;
-#define E_(M, i, j) M[(size_t)(i) * n + (j)]
-    const double rs_mn = 0.5 * (E_(R, mu, nu) + E_(R, nu, mu));
-    const double rs_ls = 0.5 * (E_(R, lam, sig) + E_(R, sig, lam));
-    const double J = 2.0 * rs_mn * rs_ls + 0.25 * (E_(D, mu, nu) * E_(P, lam, sig) + E_(P, mu, nu) * E_(D, lam, sig));
-    const double KD = E_(D, mu, sig) * E_(P, nu, lam) + E_(D, nu, sig) * E_(P, mu, lam) +
-                      E_(D, mu, lam) * E_(P, nu, sig) + E_(D, nu, lam) * E_(P, mu, sig);
-    const double KR = E_(R, sig, mu) * E_(R, lam, nu) + E_(R, sig, nu) * E_(R, lam, mu) +
-                      E_(R, mu, sig) * E_(R, nu, lam) + E_(R, mu, lam) * E_(R, nu, sig);
+    return 3 * ((size_t)ao_x * n_bf + (size_t)nx * ao_y);
+}
+
+// Permutation-averaged Gamma and Gamma^lr (eq gamma) of one Cartesian component
+// (ia, ib, ic, id) of the quartet (a b | c d) whose shell momenta are LA..LD; rec[]
+// holds the records of the ordered pairs ab ba cd dc ac ca ad da bc cb bd db.
+template <int LA, int LB, int LC, int LD>
+__device__ __forceinline__ void gamma_sym(const DerivArgs &a, const size_t rec[12], int ia, int ib, int ic, int id,
+                                          double deg, double &gf, double &gl)
+{
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    const double *B = a.dens;
+    // element (i, j) of the P (0), D (1) or R (2) block of the pair record r with row/column sizes nx, ny
+#define E_(r, k, nx, ny, i, j) B[rec[r] + (k) * (nx) * (ny) + (i) * (ny) + (j)]
+    const double rs_mn = 0.5 * (E_(0, 2, NA, NB, ia, ib) + E_(1, 2, NB, NA, ib, ia));
+    const double rs_ls = 0.5 * (E_(2, 2, NC, ND, ic, id) + E_(3, 2, ND, NC, id, ic));
+    const double J = 2.0 * rs_mn * rs_ls + 0.25 * (E_(0, 1, NA, NB, ia, ib) * E_(2, 0, NC, ND, ic, id) +
+                                                   E_(0, 0, NA, NB, ia, ib) * E_(2, 1, NC, ND, ic, id));
+    // D_ms P_nl + D_ns P_ml + D_ml P_ns + D_nl P_ms
+    const double KD = E_(6, 1, NA, ND, ia, id) * E_(8, 0, NB, NC, ib, ic) + E_(10, 1, NB, ND, ib, id) * E_(4, 0, NA, NC, ia, ic) +
+                      E_(4, 1, NA, NC, ia, ic) * E_(10, 0, NB, ND, ib, id) + E_(8, 1, NB, NC, ib, ic) * E_(6, 0, NA, ND, ia, id);
+    // R_sm R_ln + R_sn R_lm + R_ms R_nl + R_ml R_ns
+    const double KR = E_(7, 2, ND, NA, id, ia) * E_(9, 2, NC, NB, ic, ib) + E_(11, 2, ND, NB, id, ib) * E_(5, 2, NC, NA, ic, ia) +
+                      E_(6, 2, NA, ND, ia, id) * E_(8, 2, NB, NC, ib, ic) + E_(4, 2, NA, NC, ia, ic) * E_(10, 2, NB, ND, ib, id);
 #undef E_
     const double K = 0.0625 * KD + 0.25 * KR;
     gf = deg * (((a.terms & 1) ? J : 0.0) - ((a.terms & 2) ? a.alpha * K : 0.0));
     gl = deg * ((a.terms & 4) ? -a.beta * K : 0.0);
+}
+
+// Records of the 12 ordered shell pairs of the quartet (a b | c d) with AO offsets oa..od.
+template <int LA, int LB, int LC, int LD>
+__device__ __forceinline__ void pair_records(int n_bf, int oa, int ob, int oc, int od, size_t rec[12])
+{
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    rec[0] = dens_rec(n_bf, oa, NA, ob); rec[1] = dens_rec(n_bf, ob, NB, oa);
+    rec[2] = dens_rec(n_bf, oc, NC, od); rec[3] = dens_rec(n_bf, od, ND, oc);
+    rec[4] = dens_rec(n_bf, oa, NA, oc); rec[5] = dens_rec(n_bf, oc, NC, oa);
+    rec[6] = dens_rec(n_bf, oa, NA, od); rec[7] = dens_rec(n_bf, od, ND, oa);
+    rec[8] = dens_rec(n_bf, ob, NB, oc); rec[9] = dens_rec(n_bf, oc, NC, ob);
+    rec[10] = dens_rec(n_bf, ob, NB, od); rec[11] = dens_rec(n_bf, od, ND, ob);
 }
 
 // F: type of the 2D integrals, derivative products and per-primitive partial sums
@@ -335,10 +364,12 @@ k_deriv(const DerivArgs a)
             sc = M.pair_sa[ket]; sd = M.pair_sb[ket];
             const double deg = (sa != sb ? 2.0 : 1.0) * (sc != sd ? 2.0 : 1.0) * (bra != ket ? 2.0 : 1.0);
             const int oa = M.shell_ao[sa], ob = M.shell_ao[sb], oc = M.shell_ao[sc], od = M.shell_ao[sd];
+            size_t rec[12];
+            pair_records<LA, LB, LC, LD>(M.n_bf, oa, ob, oc, od, rec);
             for (int c = r; c < N; c += TEAM) {
                 const int id = c % ND, ic = (c / ND) % NC, ib = (c / (ND * NC)) % NB, ia = c / (ND * NC * NB);
                 double gf, gl;
-                gamma_sym(M, oa + ia, ob + ib, oc + ic, od + id, deg, gf, gl);
+                gamma_sym<LA, LB, LC, LD>(M, rec, ia, ib, ic, id, deg, gf, gl);
                 myG[c] = F(gf);
                 if constexpr (LR) myG[N + c] = F(gl);
             }

@@ -156,6 +156,8 @@ k_deriv_wave(const DerivArgs a)
         const double deg = (sa != sb ? 2.0 : 1.0) * (sc != sd ? 2.0 : 1.0) * (bra != ket ? 2.0 : 1.0);
         const int oa = M.shell_ao[sa], ob = M.shell_ao[sb], oc = M.shell_ao[sc], od = M.shell_ao[sd];
         F gam[CPL][2];
+        size_t rec[12];
+        pair_records<LA, LB, LC, LD>(M.n_bf, oa, ob, oc, od, rec);
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
             gam[q][0] = gam[q][1] = F(0);
@@ -163,7 +165,7 @@ k_deriv_wave(const DerivArgs a)
                 const int c = lane + q * kWave;
                 const int id = c % ND, ic = (c / ND) % NC, ib = (c / (ND * NC)) % NB, ia = c / (ND * NC * NB);
                 double gf, gl;
-                gamma_sym(M, oa + ia, ob + ib, oc + ic, od + id, deg, gf, gl);
+                gamma_sym<LA, LB, LC, LD>(M, rec, ia, ib, ic, id, deg, gf, gl);
                 gam[q][0] = F(gf);
                 gam[q][1] = F(gl);
             }

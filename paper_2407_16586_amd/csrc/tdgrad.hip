@@ -130,7 +130,7 @@ struct tdg_plan {
     DevBuf<int> d_grp_start;
     // work buffers
     DevBuf<double> d_in;                   // staging of host densities (3 n_bf^2)
-    DevBuf<double> d_Pn, d_Dn, d_Rn;
+    DevBuf<double> d_dens;                 // shell-blocked scaled densities (3 n_bf^2)
     DevBuf<double> d_mP, d_mD, d_mR;       // [n_shells^2]
     DevBuf<double> d_grad;
     DevBuf<unsigned long long> d_mx;       // max of block maxima (bit pattern of a double >= 0)
@@ -273,23 +273,27 @@ __global__ void k_schwarz(int npair, const int *pair_sa, const int *pair_sb, con
 
 // ======================================================================= a3
 // scaled densities and shell-block maxima; one thread per shell block (a, c)
+// One thread per ordered shell pair (a, c): the pair's record of the shell-blocked
+// densities (P, D = P0 + 2 PDelta and R blocks, angular factors folded in; layout in
+// deriv_kernel.hpp) and the block maxima used by the screening bound.
 __global__ void k_density_prep(int n_shells, int n_bf, const int *shell_l, const int *shell_ao, const double *ang,
-                               const double *P0, const double *PD, const double *R, double *Pn, double *Dn,
-                               double *Rn, double *mP, double *mD, double *mR, unsigned long long *mx)
+                               const double *P0, const double *PD, const double *R, double *dens, double *mP,
+                               double *mD, double *mR, unsigned long long *mx)
 {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)n_shells * n_shells) return;
     const int a = (int)(idx / n_shells), c = (int)(idx % n_shells);
     const int oa = shell_ao[a], oc = shell_ao[c], na = ncart(shell_l[a]), nc = ncart(shell_l[c]);
+    double *rec = dens + dens_rec(n_bf, oa, na, oc);
     double vp = 0.0, vd = 0.0, vr = 0.0;
     for (int i = 0; i < na; ++i)
         for (int j = 0; j < nc; ++j) {
             const size_t ij = (size_t)(oa + i) * n_bf + (oc + j), ji = (size_t)(oc + j) * n_bf + (oa + i);
             const double p = P0[ij], d = P0[ij] + 2.0 * PD[ij], rr = R[ij];
             const double s = ang[oa + i] * ang[oc + j];
-            Pn[ij] = s * p;
-            Dn[ij] = s * d;
-            Rn[ij] = s * rr;
+            rec[i * nc + j] = s * p;
+            rec[na * nc + i * nc + j] = s * d;
+            rec[2 * na * nc + i * nc + j] = s * rr;
             vp = fmax(vp, fabs(p));
             vd = fmax(vd, fabs(d));
             vr = fmax(vr, fmax(fabs(rr), fabs(R[ji])));
@@ -818,8 +822,7 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
     if ((rc = pl->d_item_cnt.alloc(std::max(nitems, 1))) || (rc = pl->d_item_off.alloc(std::max(nitems, 1))) ||
         (rc = pl->d_item_cnt32.alloc(std::max(nitems, 1))) || (rc = pl->d_item_off32.alloc(std::max(nitems, 1))) ||
         (rc = pl->d_prim_cnt.alloc(kNumClasses)) || (rc = pl->d_cand_cnt.alloc(kNumClasses)) || (rc = pl->d_mx.alloc(1)) ||
-        (rc = pl->d_grad.alloc((size_t)3 * pl->n_atoms)) || (rc = pl->d_Pn.alloc((size_t)nbf * nbf)) ||
-        (rc = pl->d_Dn.alloc((size_t)nbf * nbf)) || (rc = pl->d_Rn.alloc((size_t)nbf * nbf)) ||
+        (rc = pl->d_grad.alloc((size_t)3 * pl->n_atoms)) || (rc = pl->d_dens.alloc((size_t)3 * nbf * nbf)) ||
         (rc = pl->d_mP.alloc((size_t)ns * ns)) || (rc = pl->d_mD.alloc((size_t)ns * ns)) ||
         (rc = pl->d_mR.alloc((size_t)ns * ns)))
         return rc;
@@ -901,8 +904,8 @@ int tdg_plan_destroy(tdg_plan_t *pl)
     if (!pl) return TDG_OK;
     hipSetDevice(pl->device);
     DevBuf<double> *dbl[] = {&pl->d_coords, &pl->d_pair_Q, &pl->d_pp_p, &pl->d_pp_Px, &pl->d_pp_Py, &pl->d_pp_Pz,
-                             &pl->d_pp_c, &pl->d_pp_za, &pl->d_pp_zb, &pl->d_pp_ip, &pl->d_ang, &pl->d_in, &pl->d_Pn, &pl->d_Dn,
-                             &pl->d_Rn, &pl->d_mP, &pl->d_mD, &pl->d_mR, &pl->d_grad};
+                             &pl->d_pp_c, &pl->d_pp_za, &pl->d_pp_zb, &pl->d_pp_ip, &pl->d_ang, &pl->d_in, &pl->d_dens,
+                             &pl->d_mP, &pl->d_mD, &pl->d_mR, &pl->d_grad};
     for (auto *x : dbl) x->release();
     DevBuf<int> *ints[] = {&pl->d_shell_atom, &pl->d_shell_ao, &pl->d_shell_l, &pl->d_pair_sa, &pl->d_pair_sb,
                            &pl->d_pair_ppoff, &pl->d_pair_npp, &pl->d_pair_K, &pl->d_grp_start, &pl->d_item_cnt};
@@ -1017,8 +1020,8 @@ static int prep_and_count(tdg_plan *pl, const double *P0, const double *PD, cons
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (double *)pl->d_cand_cnt.p, (long long)kNumClasses);
     const long long nblk = (long long)ns * ns;
     hipLaunchKernelGGL(k_density_prep, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, ns, nbf,
-                       pl->d_shell_l.p, pl->d_shell_ao.p, pl->d_ang.p, dP0, dPD, dR, pl->d_Pn.p, pl->d_Dn.p,
-                       pl->d_Rn.p, pl->d_mP.p, pl->d_mD.p, pl->d_mR.p, pl->d_mx.p);
+                       pl->d_shell_l.p, pl->d_shell_ao.p, pl->d_ang.p, dP0, dPD, dR, pl->d_dens.p, pl->d_mP.p,
+                       pl->d_mD.p, pl->d_mR.p, pl->d_mx.p);
     HIP_TRY(hipGetLastError());
     ScreenArgs s = screen_args(pl);
     for (int c = 0; c < kNumClasses; ++c) {
@@ -1112,7 +1115,7 @@ static DerivArgs deriv_args(tdg_plan *pl)
     a.pair_npp = pl->d_pair_npp.p;
     a.pp_p = pl->d_pp_p.p; a.pp_Px = pl->d_pp_Px.p; a.pp_Py = pl->d_pp_Py.p; a.pp_Pz = pl->d_pp_Pz.p;
     a.pp_c = pl->d_pp_c.p; a.pp_za = pl->d_pp_za.p; a.pp_zb = pl->d_pp_zb.p; a.pp_ip = pl->d_pp_ip.p;
-    a.Pn = pl->d_Pn.p; a.Dn = pl->d_Dn.p; a.Rn = pl->d_Rn.p; a.n_bf = pl->n_bf;
+    a.dens = pl->d_dens.p; a.n_bf = pl->n_bf;
     a.omega = pl->prm.omega; a.alpha = pl->prm.alpha; a.beta = pl->prm.beta; a.terms = pl->prm.terms;
     a.grad = pl->d_grad.p; a.n_atoms = pl->n_atoms;
     a.lds_atoms = (3 * pl->n_atoms * 8 <= 24 * 1024) ? 1 : 0;
