@@ -105,8 +105,10 @@ typedef struct {
                                and the collapsed contraction; 3, 4: as 0, 2 with one lane per
                                (quartet, range) looping over the Rys roots, for classes with
                                <= 27 components (elsewhere 0, 2 run).  The transfer form (0, 3)
-                               is offered only where its kernel needs no scratch memory; there
-                               2 (4) runs instead.  Stats report the variant that ran. */
+                               is offered only for classes without p or d functions on B and D
+                               (its A->B and C->D transfers lose accuracy for tight exponents)
+                               and whose kernel needs no scratch memory; elsewhere 2 (4) runs
+                               instead.  Stats report the variant that ran. */
     double mixed_tau64; /* mixed mode: FP32 only when bound * f_ab * f_cd is below this */
     double mixed_p64;   /* mixed mode: pairs with a primitive exponent sum >= this stay FP64 */
     int64_t max_tasks;  /* screened quartets held at once (chunking of large systems); 0 = 2^31 */

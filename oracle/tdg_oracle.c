@@ -47,7 +47,16 @@
  * where |R|xy takes both orientations.  Quartets whose four shells sit on one
  * atom are skipped always (their derivative contribution is exactly zero).
  */
-#include <math.h>
+#include <tgmath.h> /* type-generic exp, sqrt, pow, erf, fabs, fmax */
+
+/* Working precision of every integral, recursion and sum: x87 extended (64-bit
+ * significand).  Inputs and outputs are FP64.  With contraction exponents up to
+ * several thousand on d shells, the horizontal transfers and the 2 zeta phi^(+) -
+ * l phi^(-) combinations of this algorithm cancel to the point where FP64 rounding
+ * reaches ~1e-8 Eh/bohr in a gradient, the size of the FP64 tolerance the GPU path
+ * is held to; the extra 11 bits keep the reference's own rounding far below it. */
+typedef long double real;
+#define ORC_PI 3.141592653589793238462643383279502884L
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -115,9 +124,9 @@ static void init_trip(void)
     trip_ready = 1;
 }
 
-static double dfact(int n) /* (n)!! with (-1)!! = 1 */
+static real dfact(int n) /* (n)!! with (-1)!! = 1 */
 {
-    double r = 1.0;
+    real r = 1.0;
     for (int k = n; k > 1; k -= 2) r *= k;
     return r;
 }
@@ -125,24 +134,31 @@ static double dfact(int n) /* (n)!! with (-1)!! = 1 */
 /* ------------------------------------------------------------------------ */
 /* Boys function F_m(T), m = 0..mmax                                         */
 
-void orc_boys(int mmax, double T, double *F)
+static void boys(int mmax, real T, real *F)
 {
     if (T < 30.0) {
         /* F_mmax(T) = exp(-T) sum_k (2T)^k / ((2mmax+1)(2mmax+3)...(2mmax+2k+1)) */
-        double term = 1.0 / (2 * mmax + 1), sum = term;
+        real term = 1.0L / (2 * mmax + 1), sum = term;
         for (int k = 1; k < 2000; ++k) {
-            term *= 2.0 * T / (2 * mmax + 2 * k + 1);
+            term *= 2.0L * T / (2 * mmax + 2 * k + 1);
             sum += term;
-            if (term < 1e-18 * sum) break;
+            if (term < 1e-22L * sum) break;
         }
-        double e = exp(-T);
+        real e = exp(-T);
         F[mmax] = e * sum;
-        for (int m = mmax; m > 0; --m) F[m - 1] = (2.0 * T * F[m] + e) / (2 * m - 1);
+        for (int m = mmax; m > 0; --m) F[m - 1] = (2.0L * T * F[m] + e) / (2 * m - 1);
     } else {
-        double e = exp(-T);
-        F[0] = 0.5 * sqrt(M_PI / T) * erf(sqrt(T));
-        for (int m = 0; m < mmax; ++m) F[m + 1] = ((2 * m + 1) * F[m] - e) / (2.0 * T);
+        real e = exp(-T);
+        F[0] = 0.5L * sqrt(ORC_PI / T) * erf(sqrt(T));
+        for (int m = 0; m < mmax; ++m) F[m + 1] = ((2 * m + 1) * F[m] - e) / (2.0L * T);
     }
+}
+
+void orc_boys(int mmax, double T, double *F)
+{
+    real Fx[ORC_MAXM + 1];
+    boys(mmax, T, Fx);
+    for (int m = 0; m <= mmax; ++m) F[m] = (double)Fx[m];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -151,29 +167,29 @@ void orc_boys(int mmax, double T, double *F)
 
 typedef struct {
     int l, np;
-    double A[3];
-    double z[ORC_MAXPRIM];
-    double c[ORC_MAXPRIM];
+    real A[3];
+    real z[ORC_MAXPRIM];
+    real c[ORC_MAXPRIM];
 } oshell_t;
 
 /* contraction coefficients for the x^l component, unit self-overlap */
-static void normalise_shell(int l, int np, const double *z, const double *d, double *c)
+static void normalise_shell(int l, int np, const real *z, const double *d, real *c)
 {
     for (int k = 0; k < np; ++k) {
-        double nk = pow(2.0 * z[k] / M_PI, 0.75) * pow(4.0 * z[k], 0.5 * l) / sqrt(dfact(2 * l - 1));
+        real nk = pow(2.0 * z[k] / ORC_PI, 0.75) * pow(4.0 * z[k], 0.5 * l) / sqrt(dfact(2 * l - 1));
         c[k] = d[k] * nk;
     }
-    double s = 0.0;
+    real s = 0.0;
     for (int i = 0; i < np; ++i)
         for (int j = 0; j < np; ++j) {
-            double zz = z[i] + z[j];
-            s += c[i] * c[j] * dfact(2 * l - 1) / pow(2.0 * zz, l) * pow(M_PI / zz, 1.5);
+            real zz = z[i] + z[j];
+            s += c[i] * c[j] * dfact(2 * l - 1) / pow(2.0 * zz, l) * pow(ORC_PI / zz, 1.5);
         }
-    double nc = 1.0 / sqrt(s);
+    real nc = 1.0 / sqrt(s);
     for (int k = 0; k < np; ++k) c[k] *= nc;
 }
 
-static double ang_norm(int lx, int ly, int lz)
+static real ang_norm(int lx, int ly, int lz)
 {
     int l = lx + ly + lz;
     return sqrt(dfact(2 * l - 1) / (dfact(2 * lx - 1) * dfact(2 * ly - 1) * dfact(2 * lz - 1)));
@@ -194,14 +210,14 @@ static void load_shell(const orc_basis_t *b, int s, oshell_t *out)
 /* out[((ia*nb+ib)*nc+ic)*nd+id], op 0: 1/r, op 1: erf(omega r)/r            */
 
 typedef struct {
-    const double *I; /* contracted [e0|f0], e over triples |e|<=Emax, f over |f|<=Fmax */
+    const real *Ic; /* contracted [e0|f0], e over triples |e|<=Emax, f over |f|<=Fmax */
     int nF;
-    double AB[3], CD[3];
+    real AB[3], CD[3];
 } hrr_ctx;
 
-static double bra_hrr(const hrr_ctx *h, const int a[3], const int b[3], int f)
+static real bra_hrr(const hrr_ctx *h, const int a[3], const int b[3], int f)
 {
-    if (b[0] + b[1] + b[2] == 0) return h->I[idx3(a) * h->nF + f];
+    if (b[0] + b[1] + b[2] == 0) return h->Ic[idx3(a) * h->nF + f];
     int i = b[0] ? 0 : (b[1] ? 1 : 2);
     int a1[3] = {a[0], a[1], a[2]}, b1[3] = {b[0], b[1], b[2]};
     a1[i] += 1;
@@ -210,7 +226,7 @@ static double bra_hrr(const hrr_ctx *h, const int a[3], const int b[3], int f)
     return bra_hrr(h, a1, b1, f) + h->AB[i] * bra_hrr(h, a, b1, f);
 }
 
-static double full_hrr(const hrr_ctx *h, const int a[3], const int b[3], const int c[3], const int d[3])
+static real full_hrr(const hrr_ctx *h, const int a[3], const int b[3], const int c[3], const int d[3])
 {
     if (d[0] + d[1] + d[2] == 0) return bra_hrr(h, a, b, idx3(c));
     int i = d[0] ? 0 : (d[1] ? 1 : 2);
@@ -221,57 +237,57 @@ static double full_hrr(const hrr_ctx *h, const int a[3], const int b[3], const i
 }
 
 static void eri_block(const oshell_t *sa, const oshell_t *sb, const oshell_t *sc, const oshell_t *sd,
-                      int op, double omega, double *out, int64_t *nprim)
+                      int op, real omega, real *out, int64_t *nprim)
 {
     init_trip();
     const int la = sa->l, lb = sb->l, lc = sc->l, ld = sd->l;
     const int Emax = la + lb, Fmax = lc + ld, L = Emax + Fmax;
     const int nE = cart_off(Emax + 1), nF = cart_off(Fmax + 1), nM = L + 1;
-    double *V = (double *)calloc((size_t)nE * nF * nM, sizeof(double));
-    double *I = (double *)calloc((size_t)nE * nF, sizeof(double));
+    real *V = (real *)calloc((size_t)nE * nF * nM, sizeof(real));
+    real *Ic = (real *)calloc((size_t)nE * nF, sizeof(real));
 #define VV(e, f, m) V[((size_t)(e) * nF + (f)) * nM + (m)]
-    double F[ORC_MAXM + 1];
-    const double *A = sa->A, *B = sb->A, *C = sc->A, *D = sd->A;
-    double AB2 = 0, CD2 = 0;
+    real F[ORC_MAXM + 1];
+    const real *A = sa->A, *B = sb->A, *C = sc->A, *D = sd->A;
+    real AB2 = 0, CD2 = 0;
     for (int k = 0; k < 3; ++k) {
         AB2 += (A[k] - B[k]) * (A[k] - B[k]);
         CD2 += (C[k] - D[k]) * (C[k] - D[k]);
     }
     for (int i = 0; i < sa->np; ++i)
         for (int j = 0; j < sb->np; ++j) {
-            double za = sa->z[i], zb = sb->z[j], p = za + zb;
-            double P[3], PA[3];
+            real za = sa->z[i], zb = sb->z[j], p = za + zb;
+            real P[3], PA[3];
             for (int k = 0; k < 3; ++k) {
                 P[k] = (za * A[k] + zb * B[k]) / p;
                 PA[k] = P[k] - A[k];
             }
-            double Kab = exp(-za * zb / p * AB2);
+            real Kab = exp(-za * zb / p * AB2);
             for (int k2 = 0; k2 < sc->np; ++k2)
                 for (int l2 = 0; l2 < sd->np; ++l2) {
-                    double zc = sc->z[k2], zd = sd->z[l2], q = zc + zd;
-                    double Q[3], QC[3], W[3], WP[3], WQ[3];
+                    real zc = sc->z[k2], zd = sd->z[l2], q = zc + zd;
+                    real Q[3], QC[3], W[3], WP[3], WQ[3];
                     for (int k = 0; k < 3; ++k) {
                         Q[k] = (zc * C[k] + zd * D[k]) / q;
                         QC[k] = Q[k] - C[k];
                     }
-                    double Kcd = exp(-zc * zd / q * CD2);
-                    double rho = p * q / (p + q), PQ2 = 0;
+                    real Kcd = exp(-zc * zd / q * CD2);
+                    real rho = p * q / (p + q), PQ2 = 0;
                     for (int k = 0; k < 3; ++k) {
                         W[k] = (p * P[k] + q * Q[k]) / (p + q);
                         WP[k] = W[k] - P[k];
                         WQ[k] = W[k] - Q[k];
                         PQ2 += (P[k] - Q[k]) * (P[k] - Q[k]);
                     }
-                    double T = rho * PQ2;
-                    double pref = 2.0 * pow(M_PI, 2.5) / (p * q * sqrt(p + q)) * Kab * Kcd *
+                    real T = rho * PQ2;
+                    real pref = 2.0 * pow(ORC_PI, 2.5) / (p * q * sqrt(p + q)) * Kab * Kcd *
                                   sa->c[i] * sb->c[j] * sc->c[k2] * sd->c[l2];
                     if (op == 0) {
-                        orc_boys(L, T, F);
+                        boys(L, T, F);
                         for (int m = 0; m <= L; ++m) VV(0, 0, m) = pref * F[m];
                     } else {
-                        double eta = omega * omega / (omega * omega + rho);
-                        orc_boys(L, eta * T, F);
-                        double s = sqrt(eta);
+                        real eta = omega * omega / (omega * omega + rho);
+                        boys(L, eta * T, F);
+                        real s = sqrt(eta);
                         for (int m = 0; m <= L; ++m) {
                             VV(0, 0, m) = pref * s * F[m];
                             s *= eta;
@@ -295,7 +311,7 @@ static void eri_block(const oshell_t *sa, const oshell_t *sb, const oshell_t *sc
                             e2 = idx3(emm);
                         }
                         for (int m = 0; m <= L - n; ++m) {
-                            double v = PA[i3] * VV(e1, 0, m) + WP[i3] * VV(e1, 0, m + 1);
+                            real v = PA[i3] * VV(e1, 0, m) + WP[i3] * VV(e1, 0, m + 1);
                             if (e2 >= 0) v += ei / (2.0 * p) * (VV(e2, 0, m) - rho / p * VV(e2, 0, m + 1));
                             VV(e, 0, m) = v;
                         }
@@ -329,7 +345,7 @@ static void eri_block(const oshell_t *sa, const oshell_t *sb, const oshell_t *sc
                                 e1 = idx3(em);
                             }
                             for (int m = 0; m <= L - ne - nf; ++m) {
-                                double v = QC[i3] * VV(e, f1, m) + WQ[i3] * VV(e, f1, m + 1);
+                                real v = QC[i3] * VV(e, f1, m) + WQ[i3] * VV(e, f1, m + 1);
                                 if (f2 >= 0) v += fi / (2.0 * q) * (VV(e, f2, m) - rho / q * VV(e, f2, m + 1));
                                 if (e1 >= 0) v += ei / (2.0 * (p + q)) * VV(e1, f1, m + 1);
                                 VV(e, f, m) = v;
@@ -337,13 +353,13 @@ static void eri_block(const oshell_t *sa, const oshell_t *sb, const oshell_t *sc
                         }
                     }
                     for (int e = 0; e < nE; ++e)
-                        for (int f = 0; f < nF; ++f) I[(size_t)e * nF + f] += VV(e, f, 0);
+                        for (int f = 0; f < nF; ++f) Ic[(size_t)e * nF + f] += VV(e, f, 0);
                     if (nprim) ++*nprim;
                 }
         }
 #undef VV
     hrr_ctx h;
-    h.I = I;
+    h.Ic = Ic;
     h.nF = nF;
     for (int k = 0; k < 3; ++k) {
         h.AB[k] = A[k] - B[k];
@@ -358,13 +374,13 @@ static void eri_block(const oshell_t *sa, const oshell_t *sb, const oshell_t *sc
                     out[((ia * nb + ib) * nc + ic) * nd + id] =
                         full_hrr(&h, trip[oa + ia], trip[ob + ib], trip[oc + ic], trip[od + id]);
     free(V);
-    free(I);
+    free(Ic);
 }
 
 /* ------------------------------------------------------------------------ */
 /* Normalised blocks: value block and the 12 centre-derivative blocks        */
 
-static void apply_ang(const oshell_t *s[4], double *blk)
+static void apply_ang(const oshell_t *s[4], real *blk)
 {
     const int n[4] = {ncart(s[0]->l), ncart(s[1]->l), ncart(s[2]->l), ncart(s[3]->l)};
     for (int ia = 0; ia < n[0]; ++ia)
@@ -380,18 +396,18 @@ static void apply_ang(const oshell_t *s[4], double *blk)
 }
 
 /* value block (normalised components) */
-static void value_block(const oshell_t *s[4], int op, double omega, double *blk, int64_t *np)
+static void value_block(const oshell_t *s[4], int op, real omega, real *blk, int64_t *np)
 {
     eri_block(s[0], s[1], s[2], s[3], op, omega, blk, np);
     apply_ang(s, blk);
 }
 
 /* der[(X*3+x)*N + comp]: d(ab|cd)/dX_x for the four centres X = a,b,c,d, explicitly */
-static void deriv_blocks(const oshell_t *s[4], int op, double omega, double *der, int64_t *np)
+static void deriv_blocks(const oshell_t *s[4], int op, real omega, real *der, int64_t *np)
 {
     const int n[4] = {ncart(s[0]->l), ncart(s[1]->l), ncart(s[2]->l), ncart(s[3]->l)};
     const int N = n[0] * n[1] * n[2] * n[3];
-    memset(der, 0, sizeof(double) * 12 * N);
+    memset(der, 0, sizeof(real) * 12 * N);
     for (int X = 0; X < 4; ++X) {
         const oshell_t *base = s[X];
         oshell_t up = *base, dn = *base;
@@ -401,8 +417,8 @@ static void deriv_blocks(const oshell_t *s[4], int op, double omega, double *der
         int nu[4] = {n[0], n[1], n[2], n[3]}, nd[4] = {n[0], n[1], n[2], n[3]};
         nu[X] = ncart(up.l);
         nd[X] = dn.l >= 0 ? ncart(dn.l) : 0;
-        double *bu = (double *)malloc(sizeof(double) * nu[0] * nu[1] * nu[2] * nu[3]);
-        double *bd = nd[X] ? (double *)malloc(sizeof(double) * nd[0] * nd[1] * nd[2] * nd[3]) : NULL;
+        real *bu = (real *)malloc(sizeof(real) * nu[0] * nu[1] * nu[2] * nu[3]);
+        real *bd = nd[X] ? (real *)malloc(sizeof(real) * nd[0] * nd[1] * nd[2] * nd[3]) : NULL;
         const oshell_t *su[4] = {s[0], s[1], s[2], s[3]}, *sd[4] = {s[0], s[1], s[2], s[3]};
         su[X] = &up;
         sd[X] = &dn;
@@ -420,7 +436,7 @@ static void deriv_blocks(const oshell_t *s[4], int op, double omega, double *der
                             tu[x] += 1;
                             int cu[4] = {c0, c1, c2, c3};
                             cu[X] = cart_pos(tu[0], tu[1], tu[2]);
-                            double v = bu[((cu[0] * nu[1] + cu[1]) * nu[2] + cu[2]) * nu[3] + cu[3]];
+                            real v = bu[((cu[0] * nu[1] + cu[1]) * nu[2] + cu[2]) * nu[3] + cu[3]];
                             if (t[x] > 0) {
                                 int td[3] = {t[0], t[1], t[2]};
                                 td[x] -= 1;
@@ -443,36 +459,36 @@ static void deriv_blocks(const oshell_t *s[4], int op, double omega, double *der
 typedef struct {
     int n;
     const double *P, *PD, *R;
-    double alpha, beta;
+    real alpha, beta;
     int terms;
 } dens_t;
 
 #define M_(X, i, j) ((X)[(size_t)(i) * d->n + (j)])
 
-static double Dm(const dens_t *d, int i, int j) { return M_(d->P, i, j) + 2.0 * M_(d->PD, i, j); }
+static real Dm(const dens_t *d, int i, int j) { return M_(d->P, i, j) + 2.0 * M_(d->PD, i, j); }
 
 /* literal Gamma and Gamma^lr of eq gamma (P -> P0, D = P0 + 2 PDelta) */
-static void gamma_literal(const dens_t *d, int mu, int nu, int lam, int sig, double *gf, double *gl)
+static void gamma_literal(const dens_t *d, int mu, int nu, int lam, int sig, real *gf, real *gl)
 {
-    double J = 2.0 * M_(d->R, nu, mu) * M_(d->R, lam, sig) + 0.5 * Dm(d, mu, nu) * M_(d->P, lam, sig);
-    double K = M_(d->R, sig, mu) * M_(d->R, lam, nu) + 0.25 * Dm(d, mu, sig) * M_(d->P, lam, nu);
+    real J = 2.0 * M_(d->R, nu, mu) * M_(d->R, lam, sig) + 0.5 * Dm(d, mu, nu) * M_(d->P, lam, sig);
+    real K = M_(d->R, sig, mu) * M_(d->R, lam, nu) + 0.25 * Dm(d, mu, sig) * M_(d->P, lam, nu);
     *gf = ((d->terms & 1) ? J : 0.0) - ((d->terms & 2) ? d->alpha * K : 0.0);
     *gl = (d->terms & 4) ? -d->beta * K : 0.0;
 }
 
 /* average of the literal Gamma over the eight index permutations that leave
  * (mu nu|lam sig) unchanged */
-static void gamma_sym(const dens_t *d, int mu, int nu, int lam, int sig, double *gf, double *gl)
+static void gamma_sym(const dens_t *d, int mu, int nu, int lam, int sig, real *gf, real *gl)
 {
-    double Rs_mn = 0.5 * (M_(d->R, mu, nu) + M_(d->R, nu, mu));
-    double Rs_ls = 0.5 * (M_(d->R, lam, sig) + M_(d->R, sig, lam));
-    double J = 2.0 * Rs_mn * Rs_ls +
+    real Rs_mn = 0.5 * (M_(d->R, mu, nu) + M_(d->R, nu, mu));
+    real Rs_ls = 0.5 * (M_(d->R, lam, sig) + M_(d->R, sig, lam));
+    real J = 2.0 * Rs_mn * Rs_ls +
                0.25 * (Dm(d, mu, nu) * M_(d->P, lam, sig) + M_(d->P, mu, nu) * Dm(d, lam, sig));
-    double KD = 0.25 * (Dm(d, mu, sig) * M_(d->P, nu, lam) + Dm(d, nu, sig) * M_(d->P, mu, lam) +
+    real KD = 0.25 * (Dm(d, mu, sig) * M_(d->P, nu, lam) + Dm(d, nu, sig) * M_(d->P, mu, lam) +
                         Dm(d, mu, lam) * M_(d->P, nu, sig) + Dm(d, nu, lam) * M_(d->P, mu, sig));
-    double KR = 0.25 * (M_(d->R, sig, mu) * M_(d->R, lam, nu) + M_(d->R, sig, nu) * M_(d->R, lam, mu) +
+    real KR = 0.25 * (M_(d->R, sig, mu) * M_(d->R, lam, nu) + M_(d->R, sig, nu) * M_(d->R, lam, mu) +
                         M_(d->R, mu, sig) * M_(d->R, nu, lam) + M_(d->R, mu, lam) * M_(d->R, nu, sig));
-    double K = 0.25 * KD + KR;
+    real K = 0.25 * KD + KR;
     *gf = ((d->terms & 1) ? J : 0.0) - ((d->terms & 2) ? d->alpha * K : 0.0);
     *gl = (d->terms & 4) ? -d->beta * K : 0.0;
 }
@@ -482,8 +498,8 @@ static void gamma_sym(const dens_t *d, int mu, int nu, int lam, int sig, double 
 /* Screening                                                                 */
 
 typedef struct {
-    double *Q;      /* [npair] Schwarz factors, unique pairs a>=b, index a(a+1)/2+b */
-    double *mP, *mD, *mR; /* [ns*ns] shell-block maxima of |P0|, |D|, |R| (both orientations) */
+    real *Q;      /* [npair] Schwarz factors, unique pairs a>=b, index a(a+1)/2+b */
+    real *mP, *mD, *mR; /* [ns*ns] shell-block maxima of |P0|, |D|, |R| (both orientations) */
 } screen_t;
 
 static int64_t pidx(int a, int b) { return a >= b ? (int64_t)a * (a + 1) / 2 + b : (int64_t)b * (b + 1) / 2 + a; }
@@ -492,34 +508,34 @@ static void screen_build(const orc_basis_t *b, const oshell_t *sh, const dens_t 
 {
     const int ns = b->n_shells;
     const int64_t np = (int64_t)ns * (ns + 1) / 2;
-    s->Q = (double *)calloc(np, sizeof(double));
-    s->mP = (double *)calloc((size_t)ns * ns, sizeof(double));
-    s->mD = (double *)calloc((size_t)ns * ns, sizeof(double));
-    s->mR = (double *)calloc((size_t)ns * ns, sizeof(double));
+    s->Q = (real *)calloc(np, sizeof(real));
+    s->mP = (real *)calloc((size_t)ns * ns, sizeof(real));
+    s->mD = (real *)calloc((size_t)ns * ns, sizeof(real));
+    s->mR = (real *)calloc((size_t)ns * ns, sizeof(real));
 #pragma omp parallel for schedule(dynamic) num_threads(nthreads)
     for (int a = 0; a < ns; ++a) {
         for (int c = 0; c <= a; ++c) {
             const oshell_t *q4[4] = {&sh[a], &sh[c], &sh[a], &sh[c]};
             int na = ncart(sh[a].l), nc = ncart(sh[c].l);
-            double *blk = (double *)malloc(sizeof(double) * na * nc * na * nc);
+            real *blk = (real *)malloc(sizeof(real) * na * nc * na * nc);
             value_block(q4, 0, 0.0, blk, NULL);
-            double mx = 0.0;
+            real mx = 0.0;
             for (int i = 0; i < na; ++i)
                 for (int j = 0; j < nc; ++j) {
-                    double v = blk[((i * nc + j) * na + i) * nc + j];
+                    real v = blk[((i * nc + j) * na + i) * nc + j];
                     if (v > mx) mx = v;
                 }
             free(blk);
             s->Q[pidx(a, c)] = sqrt(mx);
         }
         for (int c = 0; c < ns; ++c) {
-            double mp = 0, md = 0, mr = 0;
+            real mp = 0, md = 0, mr = 0;
             int oa = b->shell_ao_off[a], oc = b->shell_ao_off[c];
             for (int i = 0; i < ncart(sh[a].l); ++i)
                 for (int j = 0; j < ncart(sh[c].l); ++j) {
                     size_t ij = (size_t)(oa + i) * d->n + (oc + j), ji = (size_t)(oc + j) * d->n + (oa + i);
-                    double vp = fabs(d->P[ij]), vd = fabs(d->P[ij] + 2.0 * d->PD[ij]);
-                    double vr = fmax(fabs(d->R[ij]), fabs(d->R[ji]));
+                    real vp = fabs(d->P[ij]), vd = fabs(d->P[ij] + 2.0 * d->PD[ij]);
+                    real vr = fmax(fabs(d->R[ij]), fabs(d->R[ji]));
                     if (vp > mp) mp = vp;
                     if (vd > md) md = vd;
                     if (vr > mr) mr = vr;
@@ -536,10 +552,10 @@ static void screen_free(screen_t *s)
     free(s->Q); free(s->mP); free(s->mD); free(s->mR);
 }
 
-static double quartet_bound(const screen_t *s, int ns, int a, int b, int c, int d)
+static real quartet_bound(const screen_t *s, int ns, int a, int b, int c, int d)
 {
 #define PR(X, i, j) (s->X[(size_t)(i) * ns + (j)])
-    double m = PR(mD, a, b) * PR(mP, c, d);
+    real m = PR(mD, a, b) * PR(mP, c, d);
     m = fmax(m, PR(mP, a, b) * PR(mD, c, d));
     m = fmax(m, PR(mR, a, b) * PR(mR, c, d));
     m = fmax(m, PR(mD, a, c) * PR(mP, b, d));
@@ -555,19 +571,19 @@ static double quartet_bound(const screen_t *s, int ns, int a, int b, int c, int 
 /* ------------------------------------------------------------------------ */
 /* Per-quartet gradient contribution: out12[X*3+x] for centres a,b,c,d        */
 
-static void quartet_contrib(const orc_basis_t *b, const oshell_t *sh, const dens_t *d, double omega,
-                            int sa, int sb, int sc, int sd, int literal, double weight,
-                            double *out12, int64_t *np, double *scratch)
+static void quartet_contrib(const orc_basis_t *b, const oshell_t *sh, const dens_t *d, real omega,
+                            int sa, int sb, int sc, int sd, int literal, real weight,
+                            real *out12, int64_t *np, real *scratch)
 {
     const oshell_t *q4[4] = {&sh[sa], &sh[sb], &sh[sc], &sh[sd]};
     const int n[4] = {ncart(q4[0]->l), ncart(q4[1]->l), ncart(q4[2]->l), ncart(q4[3]->l)};
     const int N = n[0] * n[1] * n[2] * n[3];
-    double *df = scratch, *dl = scratch + 12 * N;
+    real *df = scratch, *dl = scratch + 12 * N;
     int need_f = (d->terms & 3) != 0, need_l = (d->terms & 4) != 0;
     if (need_f) deriv_blocks(q4, 0, omega, df, np);
-    else memset(df, 0, sizeof(double) * 12 * N);
+    else memset(df, 0, sizeof(real) * 12 * N);
     if (need_l) deriv_blocks(q4, 1, omega, dl, need_f ? NULL : np);
-    else memset(dl, 0, sizeof(double) * 12 * N);
+    else memset(dl, 0, sizeof(real) * 12 * N);
     const int o[4] = {b->shell_ao_off[sa], b->shell_ao_off[sb], b->shell_ao_off[sc], b->shell_ao_off[sd]};
     for (int k = 0; k < 12; ++k) out12[k] = 0.0;
     for (int i = 0; i < n[0]; ++i)
@@ -575,7 +591,7 @@ static void quartet_contrib(const orc_basis_t *b, const oshell_t *sh, const dens
             for (int k = 0; k < n[2]; ++k)
                 for (int l = 0; l < n[3]; ++l) {
                     int comp = ((i * n[1] + j) * n[2] + k) * n[3] + l;
-                    double gf, gl;
+                    real gf, gl;
                     if (literal) gamma_literal(d, o[0] + i, o[1] + j, o[2] + k, o[3] + l, &gf, &gl);
                     else gamma_sym(d, o[0] + i, o[1] + j, o[2] + k, o[3] + l, &gf, &gl);
                     for (int x = 0; x < 12; ++x) out12[x] += gf * df[x * N + comp] + gl * dl[x * N + comp];
@@ -636,13 +652,13 @@ int orc_grad(const orc_basis_t *b, const double *P0, const double *PD, const dou
     int *pa = (int *)malloc(sizeof(int) * npair), *pb = (int *)malloc(sizeof(int) * npair);
     for (int a = 0, k = 0; a < ns; ++a)
         for (int c = 0; c <= a; ++c, ++k) { pa[k] = a; pb[k] = c; }
-    double *gsum = (double *)calloc((size_t)na * 3, sizeof(double));
+    real *gsum = (real *)calloc((size_t)na * 3, sizeof(real));
     int64_t q = 0, pq = 0, sk = 0, oc = 0;
 #pragma omp parallel num_threads(nth) reduction(+ : q, pq, sk, oc)
     {
-        double *gl = (double *)calloc((size_t)na * 3, sizeof(double));
-        double *scratch = (double *)malloc(sizeof(double) * SCRATCH_N);
-        double c12[12];
+        real *gl = (real *)calloc((size_t)na * 3, sizeof(real));
+        real *scratch = (real *)malloc(sizeof(real) * SCRATCH_N);
+        real c12[12];
 #pragma omp for schedule(dynamic, 1)
         for (int64_t ab = 0; ab < npair; ++ab) {
             int a = pa[ab], bb = pb[ab];
@@ -651,7 +667,7 @@ int orc_grad(const orc_basis_t *b, const double *P0, const double *PD, const dou
                 int at = b->shell_atom[a];
                 if (b->shell_atom[bb] == at && b->shell_atom[c] == at && b->shell_atom[dd] == at) { ++oc; continue; }
                 if (prm->tau > 0 && quartet_bound(&scr, ns, a, bb, c, dd) < prm->tau) { ++sk; continue; }
-                double deg = (a != bb ? 2.0 : 1.0) * (c != dd ? 2.0 : 1.0) * (ab != cd ? 2.0 : 1.0);
+                real deg = (a != bb ? 2.0 : 1.0) * (c != dd ? 2.0 : 1.0) * (ab != cd ? 2.0 : 1.0);
                 int64_t np = 0;
                 quartet_contrib(b, sh, &d, prm->omega, a, bb, c, dd, 0, deg, c12, &np, scratch);
                 const int s4[4] = {a, bb, c, dd};
@@ -666,7 +682,7 @@ int orc_grad(const orc_basis_t *b, const double *P0, const double *PD, const dou
         free(gl);
         free(scratch);
     }
-    memcpy(grad, gsum, sizeof(double) * 3 * na);
+    for (int k = 0; k < 3 * na; ++k) grad[k] = (double)gsum[k];
     if (st) { st->quartets = q; st->prim_quartets = pq; st->skipped = sk; st->one_center = oc; }
     free(gsum); free(pa); free(pb); free(sh);
     if (prm->tau > 0) screen_free(&scr);
@@ -687,12 +703,12 @@ int orc_grad_brute(const orc_basis_t *b, const double *P0, const double *PD, con
 #endif
     oshell_t *sh = load_all(b);
     dens_t d = {b->n_bf, P0, PD, R, prm->alpha, prm->beta, prm->terms};
-    double *gsum = (double *)calloc((size_t)na * 3, sizeof(double));
+    real *gsum = (real *)calloc((size_t)na * 3, sizeof(real));
 #pragma omp parallel num_threads(nth)
     {
-        double *gl = (double *)calloc((size_t)na * 3, sizeof(double));
-        double *scratch = (double *)malloc(sizeof(double) * SCRATCH_N);
-        double c12[12];
+        real *gl = (real *)calloc((size_t)na * 3, sizeof(real));
+        real *scratch = (real *)malloc(sizeof(real) * SCRATCH_N);
+        real c12[12];
 #pragma omp for schedule(dynamic, 1) collapse(2)
         for (int a = 0; a < ns; ++a)
             for (int bb = 0; bb < ns; ++bb)
@@ -708,7 +724,7 @@ int orc_grad_brute(const orc_basis_t *b, const double *P0, const double *PD, con
         free(gl);
         free(scratch);
     }
-    memcpy(grad, gsum, sizeof(double) * 3 * na);
+    for (int k = 0; k < 3 * na; ++k) grad[k] = (double)gsum[k];
     free(gsum); free(sh);
     return 0;
 }
@@ -732,10 +748,10 @@ int orc_energy(const orc_basis_t *b, const double *P0, const double *PD, const d
     int *pa = (int *)malloc(sizeof(int) * npair), *pb = (int *)malloc(sizeof(int) * npair);
     for (int a = 0, k = 0; a < ns; ++a)
         for (int c = 0; c <= a; ++c, ++k) { pa[k] = a; pb[k] = c; }
-    double e = 0.0;
+    real e = 0.0;
 #pragma omp parallel num_threads(nth) reduction(+ : e)
     {
-        double *bf = (double *)malloc(sizeof(double) * 1296), *bl = (double *)malloc(sizeof(double) * 1296);
+        real *bf = (real *)malloc(sizeof(real) * 1296), *bl = (real *)malloc(sizeof(real) * 1296);
 #pragma omp for schedule(dynamic, 1)
         for (int64_t ab = 0; ab < npair; ++ab)
             for (int64_t cd = 0; cd <= ab; ++cd) {
@@ -743,17 +759,17 @@ int orc_energy(const orc_basis_t *b, const double *P0, const double *PD, const d
                 const oshell_t *q4[4] = {&sh[a], &sh[bb], &sh[c], &sh[dd]};
                 const int n[4] = {ncart(q4[0]->l), ncart(q4[1]->l), ncart(q4[2]->l), ncart(q4[3]->l)};
                 const int N = n[0] * n[1] * n[2] * n[3];
-                if (d.terms & 3) value_block(q4, 0, prm->omega, bf, NULL); else memset(bf, 0, sizeof(double) * N);
-                if (d.terms & 4) value_block(q4, 1, prm->omega, bl, NULL); else memset(bl, 0, sizeof(double) * N);
-                double deg = (a != bb ? 2.0 : 1.0) * (c != dd ? 2.0 : 1.0) * (ab != cd ? 2.0 : 1.0);
+                if (d.terms & 3) value_block(q4, 0, prm->omega, bf, NULL); else memset(bf, 0, sizeof(real) * N);
+                if (d.terms & 4) value_block(q4, 1, prm->omega, bl, NULL); else memset(bl, 0, sizeof(real) * N);
+                real deg = (a != bb ? 2.0 : 1.0) * (c != dd ? 2.0 : 1.0) * (ab != cd ? 2.0 : 1.0);
                 const int o[4] = {b->shell_ao_off[a], b->shell_ao_off[bb], b->shell_ao_off[c], b->shell_ao_off[dd]};
-                double s = 0.0;
+                real s = 0.0;
                 for (int i = 0; i < n[0]; ++i)
                     for (int j = 0; j < n[1]; ++j)
                         for (int k = 0; k < n[2]; ++k)
                             for (int l = 0; l < n[3]; ++l) {
                                 int comp = ((i * n[1] + j) * n[2] + k) * n[3] + l;
-                                double gf, gl;
+                                real gf, gl;
                                 gamma_sym(&d, o[0] + i, o[1] + j, o[2] + k, o[3] + l, &gf, &gl);
                                 s += gf * bf[comp] + gl * bl[comp];
                             }
@@ -783,13 +799,15 @@ int orc_quartet_contribs(const orc_basis_t *b, const double *P0, const double *P
     dens_t d = {b->n_bf, P0, PD, R, prm->alpha, prm->beta, prm->terms};
 #pragma omp parallel num_threads(nth)
     {
-        double *scratch = (double *)malloc(sizeof(double) * SCRATCH_N);
+        real *scratch = (real *)malloc(sizeof(real) * SCRATCH_N);
 #pragma omp for schedule(dynamic, 1)
         for (int64_t k = 0; k < nq; ++k) {
             int a = quartets[4 * k], bb = quartets[4 * k + 1], c = quartets[4 * k + 2], dd = quartets[4 * k + 3];
             int64_t ab = pidx(a, bb), cd = pidx(c, dd);
-            double deg = (a != bb ? 2.0 : 1.0) * (c != dd ? 2.0 : 1.0) * (ab != cd ? 2.0 : 1.0);
-            quartet_contrib(b, sh, &d, prm->omega, a, bb, c, dd, 0, deg, out + 12 * k, NULL, scratch);
+            real deg = (a != bb ? 2.0 : 1.0) * (c != dd ? 2.0 : 1.0) * (ab != cd ? 2.0 : 1.0);
+            real c12[12];
+            quartet_contrib(b, sh, &d, prm->omega, a, bb, c, dd, 0, deg, c12, NULL, scratch);
+            for (int x = 0; x < 12; ++x) out[12 * k + x] = (double)c12[x];
         }
         free(scratch);
     }
@@ -809,12 +827,12 @@ int orc_schwarz(const orc_basis_t *b, double *Q)
         for (int c = 0; c <= a; ++c) {
             const oshell_t *q4[4] = {&sh[a], &sh[c], &sh[a], &sh[c]};
             int na = ncart(sh[a].l), nc = ncart(sh[c].l);
-            double *blk = (double *)malloc(sizeof(double) * na * nc * na * nc);
+            real *blk = (real *)malloc(sizeof(real) * na * nc * na * nc);
             value_block(q4, 0, 0.0, blk, NULL);
-            double mx = 0.0;
+            real mx = 0.0;
             for (int i = 0; i < na; ++i)
                 for (int j = 0; j < nc; ++j) {
-                    double v = blk[((i * nc + j) * na + i) * nc + j];
+                    real v = blk[((i * nc + j) * na + i) * nc + j];
                     if (v > mx) mx = v;
                 }
             free(blk);
@@ -850,7 +868,7 @@ int orc_eri_tensor(const orc_basis_t *b, int op, double omega, double *out)
     if (rc) return rc;
     const int ns = b->n_shells, n = b->n_bf;
     oshell_t *sh = load_all(b);
-    double *blk = (double *)malloc(sizeof(double) * 1296);
+    real *blk = (real *)malloc(sizeof(real) * 1296);
     for (int a = 0; a < ns; ++a)
         for (int bb = 0; bb < ns; ++bb)
             for (int c = 0; c < ns; ++c)
@@ -875,8 +893,12 @@ int orc_eri_tensor(const orc_basis_t *b, int op, double omega, double *out)
 int orc_norm_coefs(const orc_basis_t *b, double *c_out)
 {
     for (int s = 0; s < b->n_shells; ++s) {
-        int off = b->shell_prim_off[s];
-        normalise_shell(b->shell_l[s], b->shell_nprim[s], b->exps + off, b->coefs + off, c_out + off);
+        const int off = b->shell_prim_off[s], np = b->shell_nprim[s];
+        if (np > ORC_MAXPRIM) return -2;
+        real z[ORC_MAXPRIM], c[ORC_MAXPRIM];
+        for (int k = 0; k < np; ++k) z[k] = b->exps[off + k];
+        normalise_shell(b->shell_l[s], np, z, b->coefs + off, c);
+        for (int k = 0; k < np; ++k) c_out[off + k] = (double)c[k];
     }
     return 0;
 }
@@ -899,11 +921,11 @@ double orc_prim_eri(const int32_t *lxyz /* [4][3] */, const double *zeta /* [4] 
     }
     if (l[0] + l[1] > ORC_MAXLR || l[2] + l[3] > ORC_MAXLR) return NAN;
     const int n[4] = {ncart(l[0]), ncart(l[1]), ncart(l[2]), ncart(l[3])};
-    double *blk = (double *)malloc(sizeof(double) * n[0] * n[1] * n[2] * n[3]);
+    real *blk = (real *)malloc(sizeof(real) * n[0] * n[1] * n[2] * n[3]);
     eri_block(&s[0], &s[1], &s[2], &s[3], op, omega, blk, NULL);
     int p[4];
     for (int k = 0; k < 4; ++k) p[k] = cart_pos(lxyz[3 * k], lxyz[3 * k + 1], lxyz[3 * k + 2]);
-    double v = blk[((p[0] * n[1] + p[1]) * n[2] + p[2]) * n[3] + p[3]];
+    real v = blk[((p[0] * n[1] + p[1]) * n[2] + p[2]) * n[3] + p[3]];
     free(blk);
     return v;
 }

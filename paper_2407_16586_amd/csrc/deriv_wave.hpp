@@ -3,11 +3,10 @@
 //
 // One wavefront evaluates one shell quartet.  For each primitive quartet the
 // Rys root slots (n full-range + n long-range) are processed in chunks:
-//   stage 1: lane (slot, direction) evaluates the root, the vertical recursion
-//            and the horizontal transfers, and writes derivative-ready 2D
-//            tables to LDS: for every index quadruple (i<=la, j<=lb, k<=lc,
-//            l<=ld) the integral G and its B, C, D derivatives
-//            2 zeta X(+1) - n X(-1);
+//   stage 1: lane (slot, direction) evaluates the root and the direct
+//            four-centre recurrence and writes derivative-ready 2D tables to
+//            LDS: for every index quadruple (i<=la, j<=lb, k<=lc, l<=ld) the
+//            integral G and its B, C, D derivatives;
 //   stage 2: lanes split the Cartesian components; each lane keeps the
 //            symmetrised Gamma of its components in registers and reads
 //            12 table values per component and root.
@@ -37,83 +36,6 @@ struct WaveClass {
     static constexpr int BLOCK = WAVES * kWave;
     static constexpr int CPL = (N + kWave - 1) / kWave;  // components per lane
 };
-
-__host__ __device__ constexpr int binom(int n, int k)
-{
-    int r = 1;
-    for (int i = 0; i < k; ++i) r = r * (n - i) / (i + 1);
-    return r;
-}
-
-// Build the derivative-ready tables of one root and one direction into LDS.
-template <int LA, int LB, int LC, int LD, typename F>
-__device__ __forceinline__ void wave_table(F *out /* [4][NBASE] */, F I0, F C00, F D00, F B10, F B01, F B00, F AB,
-                                           F CD, F zb2, F zc2, F zd2)
-{
-    constexpr int NM = LA + LB + 1, MM = LC + LD + 1;
-    constexpr int NBASE = (LA + 1) * (LB + 1) * (LC + 1) * (LD + 1);
-    F V[NM + 1][MM + 1];
-    V[0][0] = I0;
-    if constexpr (NM >= 1) V[1][0] = C00 * I0;
-#pragma unroll
-    for (int n = 1; n < NM; ++n) V[n + 1][0] = C00 * V[n][0] + (F(n) * B10) * V[n - 1][0];
-#pragma unroll
-    for (int m = 0; m < MM; ++m)
-#pragma unroll
-        for (int n = 0; n <= NM; ++n) {
-            F v = D00 * V[n][m];
-            if (m > 0) v += (F(m) * B01) * V[n][m > 0 ? m - 1 : 0];
-            if (n > 0) v += (F(n) * B00) * V[n > 0 ? n - 1 : 0][m];
-            V[n][m + 1] = v;
-        }
-    // powers of AB and CD for the binomial transfers
-    F abp[LB + 2], cdp[LD + 2];
-    abp[0] = F(1);
-    cdp[0] = F(1);
-#pragma unroll
-    for (int t = 1; t < LB + 2; ++t) abp[t] = abp[t - 1] * AB;
-#pragma unroll
-    for (int t = 1; t < LD + 2; ++t) cdp[t] = cdp[t - 1] * CD;
-#pragma unroll
-    for (int i = 0; i <= LA; ++i) {
-        // W[j][m] = (i, j | m) = sum_t C(j,t) AB^(j-t) V[i+t][m]
-        F X[LB + 2][LC + 2][LD + 2];
-#pragma unroll
-        for (int j = 0; j <= LB + 1; ++j) {
-            F W[MM + 1];
-#pragma unroll
-            for (int m = 0; m <= MM; ++m) {
-                F s = F(0);
-#pragma unroll
-                for (int t = 0; t <= j; ++t) s += (F(binom(j, t)) * abp[j - t]) * V[i + t][m];
-                W[m] = s;
-            }
-            // X[k][l] = (i, j | k, l) = sum_s C(l,s) CD^(l-s) W[k+s], k + l <= MM
-#pragma unroll
-            for (int k = 0; k <= LC + 1; ++k)
-#pragma unroll
-                for (int l = 0; l <= LD + 1; ++l) {
-                    if (k + l > MM) continue;
-                    F s = F(0);
-#pragma unroll
-                    for (int u = 0; u <= l; ++u) s += (F(binom(l, u)) * cdp[l - u]) * W[k + u];
-                    X[j][k][l] = s;
-                }
-        }
-#pragma unroll
-        for (int j = 0; j <= LB; ++j)
-#pragma unroll
-            for (int k = 0; k <= LC; ++k)
-#pragma unroll
-                for (int l = 0; l <= LD; ++l) {
-                    const int e = ((i * (LB + 1) + j) * (LC + 1) + k) * (LD + 1) + l;
-                    out[e] = X[j][k][l];
-                    out[NBASE + e] = zb2 * X[j + 1][k][l] - (j ? F(j) * X[j ? j - 1 : 0][k][l] : F(0));
-                    out[2 * NBASE + e] = zc2 * X[j][k + 1][l] - (k ? F(k) * X[j][k ? k - 1 : 0][l] : F(0));
-                    out[3 * NBASE + e] = zd2 * X[j][k][l + 1] - (l ? F(l) * X[j][k][l ? l - 1 : 0] : F(0));
-                }
-    }
-}
 
 template <int LA, int LB, int LC, int LD, bool LR, typename F, bool BATCH>
 __global__ void __launch_bounds__((WaveClass<LA, LB, LC, LD, LR, F>::BLOCK))
@@ -218,23 +140,16 @@ k_deriv_wave(const DerivArgs a)
                         const double B01 = 0.5 * iq * (1.0 - p * ipq * u);
                         const double PQd = d1 == 0 ? PQ0 : (d1 == 1 ? PQ1 : PQ2);
                         const double Pd = P[d1 == 0 ? 0 : (d1 == 1 ? 1 : 2)], Qd = Q[d1 == 0 ? 0 : (d1 == 1 ? 1 : 2)];
-                        if constexpr (sizeof(F) == sizeof(double)) {
-                            wave_table<LA, LB, LC, LD, F>(tab + s1 * TAB + d1 * 4 * NBASE, F(d1 == 2 ? pref : 1.0),
-                                                          F((Pd - Ad) - q * ipq * u * PQd),
-                                                          F((Qd - Cd) + p * ipq * u * PQd), F(B10), F(B01), F(B00), F(ABd),
-                                                          F(CDd), F(zb2), F(zc2), F(zd2));
-                        } else {
-                            const double za = M.pp_za[pb0 + ib];
-                            const DirectCoef dc =
-                                direct_coef(za, 0.5 * zb2, 0.5 * zc2, 0.5 * zd2, p, q, ip, iq, u, ipq, B10, B01, B00);
-                            const double CA = (Pd - Ad) - q * ipq * u * PQd, CB = CA + ABd;
-                            const double CCx = (Qd - Cd) + p * ipq * u * PQd, CDx = CCx + CDd;
-                            F *o = tab + s1 * TAB + d1 * 4 * NBASE;
-                            direct_tables<LA, LB, LC, LD, F>(o, F(d1 == 2 ? pref : 1.0), F(CA), F(CB), F(CCx), F(CDx),
-                                                             F(B10), F(B01), F(B00), F(zb2 * CB), F(dc.e2), F(dc.e3),
-                                                             F(dc.e4), F(zc2 * CCx), F(dc.f2), F(dc.f3), F(dc.f4),
-                                                             F(zd2 * CDx), F(dc.g2), F(dc.g3), F(dc.g4));
-                        }
+                        const double za = M.pp_za[pb0 + ib];
+                        const DirectCoef dc =
+                            direct_coef(za, 0.5 * zb2, 0.5 * zc2, 0.5 * zd2, p, q, ip, iq, u, ipq, B10, B01, B00);
+                        const double CA = (Pd - Ad) - q * ipq * u * PQd, CB = CA + ABd;
+                        const double CCx = (Qd - Cd) + p * ipq * u * PQd, CDx = CCx + CDd;
+                        F *o = tab + s1 * TAB + d1 * 4 * NBASE;
+                        direct_tables<LA, LB, LC, LD, F>(o, F(d1 == 2 ? pref : 1.0), F(CA), F(CB), F(CCx), F(CDx),
+                                                         F(B10), F(B01), F(B00), F(zb2 * CB), F(dc.e2), F(dc.e3),
+                                                         F(dc.e4), F(zc2 * CCx), F(dc.f2), F(dc.f3), F(dc.f4),
+                                                         F(zd2 * CDx), F(dc.g2), F(dc.g3), F(dc.g4));
                     }
                     wave_sync();
 #pragma unroll

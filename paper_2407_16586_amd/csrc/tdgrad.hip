@@ -143,8 +143,8 @@ struct tdg_plan {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ev_cls[kNumClasses + 1] = {};
     int variant[2][kNumClasses];           // kernel variant per (precision, class): 0 team, 1 wavefront, 2 direct team
-    bool tf_ok[2][2][kNumClasses];         // transfer-form variants (0, 3) offered: their kernel keeps its
-                                           // tables in registers (no scratch memory); else 2 (4) runs
+    bool tf_ok[2][2][kNumClasses];         // transfer-form variants (0, 3) offered: no p/d on B or D and
+                                           // the kernel keeps its tables in registers; else 2 (4) runs
     int split[kNumClasses];                // 1: the FP32-routed quartets of the class run in FP32; 0: the
                                            // whole class runs in FP64 (measured faster by the autotuner)
     std::vector<double> pair_pmax;         // largest primitive exponent sum of each sorted pair
@@ -832,8 +832,14 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
     const bool lr = (pl->prm.terms & 4) && pl->prm.beta != 0.0;
     for (int pr = 0; pr < 2; ++pr)
         for (int c = 0; c < kNumClasses; ++c) {
-            pl->tf_ok[pr][0][c] = kScratch[c](0, pr, lr) == 0;
-            pl->tf_ok[pr][1][c] = class_ncomp(c) <= 27 && kScratch[c](3, pr, lr) == 0;
+            // the transfer form moves momentum A->B and C->D; with p or d functions on B or
+            // D those steps cancel for tight exponents, so it is offered only when
+            // l_B = l_D = 0 (and its kernel needs no scratch memory)
+            int pb, pk;
+            class_pk(c, pb, pk);
+            const bool no_transfer = kPairL[pb][1] == 0 && kPairL[pk][1] == 0;
+            pl->tf_ok[pr][0][c] = no_transfer && kScratch[c](0, pr, lr) == 0;
+            pl->tf_ok[pr][1][c] = no_transfer && class_ncomp(c) <= 27 && kScratch[c](3, pr, lr) == 0;
             int v = pl->prm.kernel_variant >= 0 ? pl->prm.kernel_variant : default_variant(c);
             if ((v == 3 || v == 4) && class_ncomp(c) > 27) v = v == 3 ? 0 : 2;
             if (v == 0 && !pl->tf_ok[pr][0][c]) v = 2;

@@ -10,15 +10,18 @@ Shapes follow the paper's workload class (section III.A): protein-like
 first-row/hydrogen systems with a contracted core s shell, split valence and
 one d polarisation shell on heavy atoms, Cartesian functions, l <= 2.
 
-Basis recipe per atom, shaped like the def2-SVP basis of the paper's runs
-(section III.A): a segmented [3s2p1d] / [2s1p] contraction with exponents drawn
-log-uniformly from a range per shell (sorted descending within a shell) and
-positive contraction coefficients exp(N(0, 0.5)), normalised by the consumer:
-  heavy : s(6) [3, 5000]  s(1) [0.3, 1.0]  s(1) [0.08, 0.3]
-          p(3) [0.4, 15]  p(1) [0.1, 0.3]  d(1) [0.4, 1.5]
-          -> 6 shells, 13 prims, 15 Cartesian functions
-  H     : s(3) [0.4, 15]  s(1) [0.1, 0.25] p(1) [0.6, 1.2]
-          -> 3 shells,  5 prims,  5 functions
+Basis recipe per atom (the contraction pattern of the paper's def2-SVP runs,
+section III.A: [3s2p1d] on heavy atoms, [2s1p] on H), in two variants:
+  "stated" (default; the recipe the workloads are defined with): exponents
+      log-uniform in [0.1, 5000] for every shell, sorted descending within a
+      shell; contraction coefficients N(0, 1), normalised by the consumer;
+  "svp": exponent ranges per shell shaped like def2-SVP and positive
+      coefficients exp(N(0, 0.5)):
+        heavy s(6) [3, 5000]  s(1) [0.3, 1.0]  s(1) [0.08, 0.3]
+              p(3) [0.4, 15]  p(1) [0.1, 0.3]  d(1) [0.4, 1.5]
+        H     s(3) [0.4, 15]  s(1) [0.1, 0.25] p(1) [0.6, 1.2]
+  heavy : s(6) s(1) s(1) p(3) p(1) d(1)  -> 6 shells, 13 prims, 15 Cartesian functions
+  H     : s(3) s(1) p(1)                 -> 3 shells,  5 prims,  5 functions
 
 Densities (definitions of section II.A): P0 = occ * C_o C_o^T,
 R = C_o X C_v^T with X an n_occ x n_vir amplitude matrix of unit Frobenius
@@ -35,10 +38,21 @@ import numpy as np
 
 BASE_SEED = 20240716
 
-# (l, primitives, exponent range) per shell
-HEAVY_RECIPE = ((0, 6, (3.0, 5000.0)), (0, 1, (0.3, 1.0)), (0, 1, (0.08, 0.3)),
-                (1, 3, (0.4, 15.0)), (1, 1, (0.1, 0.3)), (2, 1, (0.4, 1.5)))
-H_RECIPE = ((0, 3, (0.4, 15.0)), (0, 1, (0.1, 0.25)), (1, 1, (0.6, 1.2)))
+# (l, primitives, exponent range) per shell, per recipe; coefficient law per recipe
+_WIDE = (0.1, 5000.0)
+RECIPES = {
+    "stated": {
+        "heavy": ((0, 6, _WIDE), (0, 1, _WIDE), (0, 1, _WIDE), (1, 3, _WIDE), (1, 1, _WIDE), (2, 1, _WIDE)),
+        "H": ((0, 3, _WIDE), (0, 1, _WIDE), (1, 1, _WIDE)),
+        "coef": lambda rng, k: rng.standard_normal(k),
+    },
+    "svp": {
+        "heavy": ((0, 6, (3.0, 5000.0)), (0, 1, (0.3, 1.0)), (0, 1, (0.08, 0.3)),
+                  (1, 3, (0.4, 15.0)), (1, 1, (0.1, 0.3)), (2, 1, (0.4, 1.5))),
+        "H": ((0, 3, (0.4, 15.0)), (0, 1, (0.1, 0.25)), (1, 1, (0.6, 1.2))),
+        "coef": lambda rng, k: np.exp(0.5 * rng.standard_normal(k)),
+    },
+}
 
 # range-separated hybrid parameters of the paper's production functional
 OMEGA = 0.3
@@ -104,15 +118,15 @@ class Molecule:
             assert self.P0.shape == (n, n) and self.PD.shape == (n, n) and self.R.shape == (n, n)
 
 
-def _build_basis(rng: np.random.Generator, Z: np.ndarray):
+def _build_basis(rng: np.random.Generator, Z: np.ndarray, recipe: str = "stated"):
+    rec = RECIPES[recipe]
     sh_atom, sh_l, sh_np, sh_po, sh_ao = [], [], [], [], []
     exps, coefs = [], []
     ao = 0
     for ia, z in enumerate(Z):
-        recipe = H_RECIPE if z == 1 else HEAVY_RECIPE
-        for l, k, (elo, ehi) in recipe:
+        for l, k, (elo, ehi) in (rec["H"] if z == 1 else rec["heavy"]):
             e = np.sort(np.exp(rng.uniform(math.log(elo), math.log(ehi), size=k)))[::-1]
-            c = np.exp(0.5 * rng.standard_normal(k))
+            c = rec["coef"](rng, k)
             sh_atom.append(ia)
             sh_l.append(l)
             sh_np.append(k)
@@ -199,8 +213,8 @@ def _sphere_geometry(rng, n_atoms, density=0.1, dmin=1.8, max_tries=10_000_000):
     return pts
 
 
-def _assemble(name, rng, coords, Z, n_occ=None, occ_frac=0.1, with_dens=True):
-    basis = _build_basis(rng, Z)
+def _assemble(name, rng, coords, Z, n_occ=None, occ_frac=0.1, with_dens=True, recipe="stated"):
+    basis = _build_basis(rng, Z, recipe)
     sh_atom, sh_l, sh_np, sh_po, sh_ao, exps, coefs = basis
     n_bf = int(sh_ao[-1] + ncart(int(sh_l[-1])))
     if n_occ is None:
@@ -223,7 +237,7 @@ def config0(seed_offset: int = 0) -> Molecule:
     return _assemble("six-atom box (50 functions)", rng, coords, Z, n_occ=8)
 
 
-def chain(n_heavy: int = 20, seed: int = BASE_SEED + 1, n_occ: int | None = 50) -> Molecule:
+def chain(n_heavy: int = 20, seed: int = BASE_SEED + 1, n_occ: int | None = 50, recipe: str = "stated") -> Molecule:
     """Alkane-like chain: heavy atoms every 2.9 bohr along x with +-0.2 bohr jitter,
     two H per heavy atom at 2.06 bohr."""
     rng = np.random.default_rng(seed)
@@ -242,13 +256,13 @@ def chain(n_heavy: int = 20, seed: int = BASE_SEED + 1, n_occ: int | None = 50) 
     assert dm.min() >= 1.8, dm.min()
     if n_occ is None:
         n_occ = 5 * n_heavy // 2
-    return _assemble(f"{3 * n_heavy}-atom chain", rng, coords, np.array(Z), n_occ=n_occ)
+    return _assemble(f"{3 * n_heavy}-atom chain", rng, coords, np.array(Z), n_occ=n_occ, recipe=recipe)
 
 
-def config1() -> Molecule:
+def config1(recipe: str = "stated") -> Molecule:
     """60-atom alkane-like chain (20 heavy + 40 H, 500 functions), n_occ = 50."""
-    m = chain(20, BASE_SEED + 1, 50)
-    m.name = "60-atom chain (500 functions)"
+    m = chain(20, BASE_SEED + 1, 50, recipe)
+    m.name = "60-atom chain (500 functions)" + ("" if recipe == "stated" else f", {recipe} exponents")
     return m
 
 
@@ -272,7 +286,7 @@ def config2(n_mol: int = 64, with_dens: bool = True) -> list[Molecule]:
             for i, n in enumerate(sizes)]
 
 
-def water_cluster(n_waters: int, seed: int, with_dens: bool = True) -> Molecule:
+def water_cluster(n_waters: int, seed: int, with_dens: bool = True, recipe: str = "stated") -> Molecule:
     """n waters on the sites of a 6x6x4 cubic lattice (5.9 bohr) nearest its centroid, +-0.4 bohr
     jitter, O-H 1.81 bohr, HOH 104.5 degrees, random orientations; 5 occupied orbitals per water."""
     rng = np.random.default_rng(seed)
@@ -293,7 +307,7 @@ def water_cluster(n_waters: int, seed: int, with_dens: bool = True) -> Molecule:
             pts.append(o + q @ a)
             Z.append(z)
     return _assemble(f"{n_waters} waters", rng, np.array(pts), np.array(Z), n_occ=5 * n_waters,
-                     with_dens=with_dens)
+                     with_dens=with_dens, recipe=recipe)
 
 
 def config3(with_dens: bool = True) -> Molecule:

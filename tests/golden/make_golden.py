@@ -18,6 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CASES = {
     # 60-atom chain, 500 Cartesian functions, density-multiplied Schwarz threshold 1e-10
     "chain60_tau1e-10": dict(mol=synth.config1, tau=1e-10),
+    # the same chain with def2-SVP-shaped exponent ranges and positive coefficients
+    "chain60svp_tau1e-10": dict(mol=lambda: synth.config1("svp"), tau=1e-10),
 }
 
 

@@ -41,19 +41,27 @@ def test_boys_special_values(oracle_lib):
 
 # ------------------------------------------------------------- s-type integrals
 def _ss_closed(za, zb, zc, zd, A, B, C, D, omega=None):
+    """Closed form evaluated at 40 digits (the inputs are exact doubles), so the reference's
+    own rounding (exp of arguments of several hundred) does not enter the comparison."""
+    import mpmath
+    mp = mpmath.mp
+    mp.dps = 40
+    f = mpmath.mpf
+    za, zb, zc, zd = f(za), f(zb), f(zc), f(zd)
+    A, B, C, D = ([f(x) for x in v] for v in (A, B, C, D))
     p, q = za + zb, zc + zd
-    P = (za * A + zb * B) / p
-    Q = (zc * C + zd * D) / q
-    Kab = math.exp(-za * zb / p * np.sum((A - B) ** 2))
-    Kcd = math.exp(-zc * zd / q * np.sum((C - D) ** 2))
-    R = np.linalg.norm(P - Q)
+    P = [(za * a + zb * b) / p for a, b in zip(A, B)]
+    Q = [(zc * c + zd * d) / q for c, d in zip(C, D)]
+    Kab = mpmath.exp(-za * zb / p * sum((a - b) ** 2 for a, b in zip(A, B)))
+    Kcd = mpmath.exp(-zc * zd / q * sum((c - d) ** 2 for c, d in zip(C, D)))
+    R = mpmath.sqrt(sum((x - y) ** 2 for x, y in zip(P, Q)))
     a = p * q / (p + q)
     if omega is not None:
-        a = 1.0 / (1.0 / p + 1.0 / q + 1.0 / omega ** 2)
-    pre = Kab * Kcd * (math.pi ** 2 / (p * q)) ** 1.5
-    if R < 1e-12:
-        return pre * 2.0 * math.sqrt(a / math.pi)
-    return pre * math.erf(math.sqrt(a) * R) / R
+        a = 1 / (1 / p + 1 / q + 1 / f(omega) ** 2)
+    pre = Kab * Kcd * (mpmath.pi ** 2 / (p * q)) ** f(1.5)
+    if R < f(1e-12):
+        return float(pre * 2 * mpmath.sqrt(a / mpmath.pi))
+    return float(pre * mpmath.erf(mpmath.sqrt(a) * R) / R)
 
 
 def test_ss_closed_form(oracle_lib):
