@@ -89,9 +89,10 @@ typedef struct {
                            per-primitive partial sums in FP32 for quartets routed to FP32; Rys
                            roots, weights, prefactors and all accumulation in FP64.  A quartet
                            is routed to FP32 when bound * f_ab * f_cd < mixed_tau64 and every
-                           primitive exponent sum is < mixed_p64, with f the pair's FP32
-                           error-amplification factor max_k (1 + |AB| zeta_b/sqrt(p))^(lb+1)
-                           sqrt(max zeta) over its primitive pairs */
+                           primitive exponent sum is < mixed_p64, with f the square root of
+                           the pair's largest primitive exponent (the scale a centre
+                           derivative adds to an integral); classes where FP64 measures faster
+                           run their FP32-routed quartets in FP64 (see autotune) */
     int32_t terms;      /* bit 1: Coulomb-type (J) terms, bit 2: full-range exchange (alpha),
                            bit 4: long-range exchange (beta); 7 = all */
     int32_t autotune;   /* 1: on the plan's first tdg_grad_jk call, time the kernel variants

@@ -796,8 +796,7 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
         for (int k = off[i]; k < off[i] + cnt[i]; ++k) {
             pl->pair_pmax[i] = std::max(pl->pair_pmax[i], pp[0][k]);
             pl->pair_pmin[i] = std::min(pl->pair_pmin[i], pp[0][k]);
-            const double h = 1.0 + ab * pp[6][k] / std::sqrt(pp[0][k]);
-            const double f = std::pow(h, lb + 1) * std::sqrt(std::max(pp[5][k], pp[6][k]));
+            const double f = std::sqrt(std::max(pp[5][k], pp[6][k]));
             pl->pair_famp[i] = std::max(pl->pair_famp[i], f);
         }
     }

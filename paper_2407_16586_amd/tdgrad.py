@@ -124,7 +124,7 @@ class Plan:
     """A plan for one molecule (geometry + basis); see tdg_plan_create."""
 
     def __init__(self, mol, omega=None, alpha=None, beta=None, schwarz_tol=1e-10, terms=TERMS_ALL,
-                 precision=0, device=0, autotune=True, kernel_variant=-1, mixed_tau64=1.0,
+                 precision=0, device=0, autotune=True, kernel_variant=-1, mixed_tau64=0.1,
                  mixed_p64=float("inf"), max_tasks=0):
         self._keep = [np.ascontiguousarray(mol.coords, dtype=np.float64)]
         for name in ("shell_atom", "shell_l", "shell_nprim", "shell_prim_off", "shell_ao_off"):
