@@ -242,6 +242,21 @@ def test_chain60_mixed_against_stored_oracle(tdg):
     assert err <= MIXED_TOL
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_chain60_svp_against_stored_oracle(tdg, precision):
+    """The same chain with def2-SVP-shaped exponent ranges (26.5M surviving quartets) against
+    the oracle's stored gradient: FP64 within 1e-8, mixed within 1e-6."""
+    from paper_2407_16586_amd import synth
+    ref = json.load(open(os.path.join(HERE, "golden", "chain60svp_tau1e-10.json")))
+    m = synth.config1("svp")
+    p = tdg.Plan(m, schwarz_tol=ref["tau"], precision=precision)
+    g, st = p.grad(m.P0, m.PD, m.R, stats=True)
+    err = np.abs(g - np.array(ref["grad"])).max()
+    _say("chain60svp", precision, "max-abs", err, "quartets", st["quartets"], ref["oracle_stats"]["quartets"])
+    assert abs(st["quartets"] - ref["oracle_stats"]["quartets"]) <= 0.0001 * ref["oracle_stats"]["quartets"]
+    assert err <= (TOL if precision == 0 else MIXED_TOL)
+
+
 # ------------------------------------------------------------------ batched launch
 def _batch_molecules():
     from paper_2407_16586_amd import synth
