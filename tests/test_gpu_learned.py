@@ -28,3 +28,27 @@ def test_learned_veto_gain(oracle_lib):
           "skipped", st and st["ml_skipped"], "err", err, flush=True)
     assert thr is not None and err <= 1e-6
     assert st["ml_skipped"] > 0 and st["quartets"] + st["ml_skipped"] == st0["quartets"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_veto_with_compacted_segments(precision):
+    """A veto that removes every quartet whose bound is below tau_hi leaves gaps inside every
+    task segment after compaction; the mixed path (which may run a class's FP32 segment with
+    the FP64 kernel) must still evaluate exactly the kept quartets: it agrees with the FP64
+    path under the same veto, and the kept plus vetoed counts add up."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    import molecules
+    from paper_2407_16586_amd import tdgrad
+    m = molecules.small_mixed(6)
+    est = tdgrad.Estimator(seed=5)
+    res = {}
+    for prec in (0, precision):
+        p = tdgrad.Plan(m, schwarz_tol=1e-10, precision=prec)
+        g0, s0 = p.grad(m.P0, m.PD, m.R, stats=True)
+        p.set_screen_model(est, 100.0, 1e-3)  # veto everything the bound does not keep
+        g, st = p.grad(m.P0, m.PD, m.R, stats=True)
+        assert st["ml_skipped"] > 0 and st["quartets"] > 0
+        assert st["quartets"] + st["ml_skipped"] == s0["quartets"]
+        res[prec] = g
+    assert np.abs(res[precision] - res[0]).max() <= (1e-12 if precision == 0 else 1e-6)

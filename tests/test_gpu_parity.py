@@ -257,6 +257,27 @@ def test_chain60_svp_against_stored_oracle(tdg, precision):
     assert err <= (TOL if precision == 0 else MIXED_TOL)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_screening_overflow_and_reuse(tdg, precision):
+    """After one call the task regions are sized from its survivor counts and later calls
+    screen in one fused launch. Densities scaled by 1e-5 leave few survivors; the next call
+    with the real densities overflows those regions and falls back to the count and fill
+    passes; the call after that runs fused with re-learned regions. Both equal a fresh plan's
+    gradient (same quartets, summation order aside)."""
+    from paper_2407_16586_amd import synth
+    m = synth.random_molecule(4, 6, seed=77)
+    p = tdg.Plan(m, schwarz_tol=1e-10, precision=precision)
+    _, s_small = p.grad(1e-5 * m.P0, 1e-5 * m.PD, 1e-5 * m.R, stats=True)
+    g1, s1 = p.grad(m.P0, m.PD, m.R, stats=True)
+    g2, s2 = p.grad(m.P0, m.PD, m.R, stats=True)
+    fresh = tdg.Plan(m, schwarz_tol=1e-10, precision=precision)
+    g0, s0 = fresh.grad(m.P0, m.PD, m.R, stats=True)
+    _say("fused", precision, s_small["quartets"], s1["quartets"], s2["quartets"], s0["quartets"])
+    assert s_small["quartets"] * 4 < s1["quartets"] == s2["quartets"] == s0["quartets"]
+    tol = 1e-11 if precision == 0 else MIXED_TOL
+    assert np.abs(g1 - g0).max() <= tol and np.abs(g2 - g0).max() <= tol
+
+
 # ------------------------------------------------------------------ batched launch
 def _batch_molecules():
     from paper_2407_16586_amd import synth
