@@ -12,7 +12,10 @@ One step = one call of the library's gradient entry point with the densities
 already resident in device memory: density preparation, screening and task
 generation, all 21 ERI-derivative class kernels and the per-atom reduction.
 
-Prints one JSON line (see README/DESIGN for the fields).
+Prints one JSON line: the metric, the headline value and its configuration, both paths'
+figures, the roofline of the dominant class kernel (achieved algorithmic FLOP rate against
+the FP64 vector peak, and its HBM bytes per launch when the committed counter summary under
+profiles/ was taken on the current kernel sources) and the CPU oracle's rate on a sample.
 """
 import argparse
 import json
@@ -25,6 +28,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ERI-deriv quartets/s & J/K-grad wall s, mixed vs FP64 on 1 GPU @1e-6 Eh/bohr"
 FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def _sources_sha():
+    """sha256 (16 hex digits) over the HIP sources, in path order."""
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2407_16586_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(cls, variant, prec):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration) of one
+    class kernel from the committed counter summaries, or None when none was taken on the
+    current sources."""
+    import glob
+    sha, key = _sources_sha(), "".join(map(str, cls))
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.txt"))):
+        with open(path) as fh:
+            for line in fh:
+                f = line.split()
+                if len(f) >= 7 and f[0] == "traffic" and f[1] == key and f[2] == str(variant) and f[3] == prec \
+                        and f[4] == sha:
+                    return int(f[5]) + int(f[6])
+    return None
 
 
 def cpu_baseline(mol, target_s=15.0, seed=7):
@@ -122,6 +153,14 @@ def main():
         prims = np.array(st["class_prim_quartets"], dtype=np.float64)
         flops = np.array([FLOPS_PER_PRIM[c] for c in tdgrad.CLASSES], dtype=np.float64) * prims
         dom = int(np.argmax(class_ms))
+        # the dominant class's kernel: its FP64 kernel unless the class ran its (larger)
+        # FP32-routed list with the FP32 kernel
+        cv = st["class_variant"][dom]
+        n32 = st["class_fp32_quartets"][dom]
+        if not (cv & 64) and n32 * 2 > st["class_quartets"][dom]:
+            dvar, dprec = (cv >> 3) & 7, "fp32"
+        else:
+            dvar, dprec = cv & 7, "fp64"
         ms_step = 1e3 * dt / args.steps
         achieved = flops[dom] / (class_ms[dom] * 1e-3) / 1e12
         all_tflops = flops.sum() / (class_ms.sum() * 1e-3) / 1e12
@@ -130,9 +169,10 @@ def main():
         return {
             "ms_step": ms_step, "plan_s": plan_s, "grad": g, "stats": st, "class_ms": class_ms,
             "quartets": st["quartets"], "value": st["quartets"] / (ms_step * 1e-3),
-            "roofline": {"bound": "alu", "kernel": "k_deriv" + str(tdgrad.CLASSES[dom]),
+            "roofline": {"bound": "alu", "kernel": f"k_deriv{tdgrad.CLASSES[dom]} variant {dvar} {dprec}",
                          "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                         "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+                         "traffic": _traffic(tdgrad.CLASSES[dom], dvar, dprec),
                          "all_classes_achieved": all_tflops,
                          "all_classes_frac": all_tflops / FP64_VALU_PEAK_TFLOPS},
         }
