@@ -4,9 +4,10 @@ Workload: the 60-atom alkane-like chain (20 heavy + 40 H atoms, 500 Cartesian
 functions, l <= 2, contraction degrees up to 6), seeded synthetic densities,
 omega = 0.3, alpha = 0.157706, beta = 0.842294, density-multiplied Schwarz
 threshold 1e-10, all terms (J, full-range K, long-range K).  Both the FP64 path
-and the mixed path (FP32 2D integrals for routed quartets, FP64 roots and sums)
-are timed; the headline value is the faster one whose gradient stays within
-1e-6 Eh/bohr of the FP64 result.
+and the mixed path (FP32 2D integrals for routed quartets, FP64 roots and sums;
+by default every class runs the precision its autotuning measured faster) are
+timed; the headline value is the faster one whose gradient stays within 1e-6
+Eh/bohr of the FP64 result.
 
 One step = one call of the library's gradient entry point with the densities
 already resident in device memory: density preparation, screening and task
@@ -42,18 +43,29 @@ def _sources_sha():
     return h.hexdigest()[:16]
 
 
-def _traffic(cls, variant, prec):
+def launch_quartets(stats, c, prec):
+    """Quartets in class c's launch of the given precision ("fp64" or "fp32"): a class in
+    mixed mode runs its FP32-routed quartets in their own FP32 launch unless the autotuner
+    kept the class in one FP64 launch (class_variant bit 6)."""
+    n, n32 = stats["class_quartets"][c], stats["class_fp32_quartets"][c]
+    split = n32 > 0 and not (stats["class_variant"][c] & 64)
+    if prec == "fp32":
+        return n32 if split else 0
+    return n - n32 if split else n
+
+
+def _traffic(cls, variant, prec, nq):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration) of one
     class kernel from the committed counter summaries, or None when none was taken on the
-    current sources."""
+    current sources for a launch of the same number of quartets."""
     import glob
     sha, key = _sources_sha(), "".join(map(str, cls))
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.txt"))):
         with open(path) as fh:
             for line in fh:
                 f = line.split()
-                if len(f) >= 7 and f[0] == "traffic" and f[1] == key and f[2] == str(variant) and f[3] == prec \
-                        and f[4] == sha:
+                if len(f) >= 8 and f[0] == "traffic" and f[1] == key and f[2] == str(variant) and f[3] == prec \
+                        and f[4] == sha and f[7] == str(nq):
                     return int(f[5]) + int(f[6])
     return None
 
@@ -113,6 +125,10 @@ def main():
     ap.add_argument("--path", choices=("both", "fp64", "mixed"), default="both",
                     help="precision paths to time; with both, the headline is the mixed path when it "
                          "is faster and within 1e-6 Eh/bohr of the FP64 path")
+    ap.add_argument("--mixed-tau64", type=float, default=float("inf"),
+                    help="mixed path's routing bound (a quartet runs in FP32 when its density-weighted "
+                         "bound times the pair exponent scales is below this); infinity routes on class "
+                         "timing alone, and the headline still requires 1e-6 Eh/bohr against FP64")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy MIB MiB device-to-device (a plain copy of known "
                          "size that calibrates the HBM counters of a profiling run)")
@@ -136,7 +152,7 @@ def main():
     def run_path(precision):
         print(f"bench: plan for {mol.name}, precision {precision}", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
-        plan = tdgrad.Plan(mol, schwarz_tol=1e-10, precision=precision)
+        plan = tdgrad.Plan(mol, schwarz_tol=1e-10, precision=precision, mixed_tau64=args.mixed_tau64)
         plan_s = time.perf_counter() - t0
         out = torch.zeros((mol.n_atoms, 3), dtype=torch.float64, device=dev)
         for _ in range(args.warmup):
@@ -172,7 +188,8 @@ def main():
             "roofline": {"bound": "alu", "kernel": f"k_deriv{tdgrad.CLASSES[dom]} variant {dvar} {dprec}",
                          "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-                         "traffic": _traffic(tdgrad.CLASSES[dom], dvar, dprec),
+                         "traffic": _traffic(tdgrad.CLASSES[dom], dvar, dprec, launch_quartets(st, dom, dprec)),
+                         "launch_quartets": launch_quartets(st, dom, dprec),
                          "all_classes_achieved": all_tflops,
                          "all_classes_frac": all_tflops / FP64_VALU_PEAK_TFLOPS},
         }
@@ -202,7 +219,9 @@ def main():
         "config": {"workload": "60-atom alkane-like chain, 500 Cartesian functions (l<=2), "
                                "J + full-range K + long-range K, omega=0.3, tau=1e-10",
                    "n_atoms": mol.n_atoms, "n_bf": mol.n_bf, "tau": 1e-10,
-                   "precision": "mixed" if use_mixed else "fp64"},
+                   "precision": "mixed" if use_mixed else "fp64",
+                   "mixed_tau64": (str(args.mixed_tau64) if args.mixed_tau64 == float("inf")
+                                   else args.mixed_tau64) if use_mixed else None},
         "wall_s": head["ms_step"] * 1e-3,
         "quartets": head["quartets"],
         "prim_quartets": st["prim_quartets"],
@@ -212,6 +231,8 @@ def main():
         "roofline": head["roofline"],
         "class_ms": {str(c): round(float(m), 4) for c, m in zip(tdgrad.CLASSES, head["class_ms"])},
         "class_variant": st["class_variant"],
+        "class_quartets": st["class_quartets"],
+        "class_fp32_quartets": st["class_fp32_quartets"],
     }
     if fp64:
         rec["fp64"] = {"value": fp64["value"], "wall_s": fp64["ms_step"] * 1e-3,

@@ -110,8 +110,12 @@ typedef struct {
                                (its A->B and C->D transfers lose accuracy for tight exponents)
                                and whose kernel needs no scratch memory; elsewhere 2 (4) runs
                                instead.  Stats report the variant that ran. */
-    double mixed_tau64; /* mixed mode: FP32 only when bound * f_ab * f_cd is below this */
-    double mixed_p64;   /* mixed mode: pairs with a primitive exponent sum >= this stay FP64 */
+    double mixed_tau64; /* mixed mode: FP32 only when bound * f_ab * f_cd is below this (the
+                           Python binding's default is 0.1); INFINITY routes on class timing
+                           alone, which is fastest but leaves the error unbounded by the
+                           router: it scales with the largest quartet contributions */
+    double mixed_p64;   /* mixed mode: pairs with a primitive exponent sum >= this stay FP64
+                           (INFINITY: no exponent cap) */
     int64_t max_tasks;  /* screened quartets held at once (chunking of large systems); 0 = 2^31 */
 } tdg_params_t;
 

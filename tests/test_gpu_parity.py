@@ -208,16 +208,17 @@ MIXED_TOL = 1e-6
 @pytest.mark.parametrize("variant", [-1, 0, 1, 2, 3, 4])
 def test_mixed_precision_small(tdg, oracle_lib, mol0, variant):
     """FP32 2D integrals (FP64 roots, prefactors, sums) within 1e-6 of the FP64 oracle,
-    with every quartet routed to FP32 (thresholds at infinity) and with the defaults."""
+    with every quartet routed to FP32 (thresholds at infinity) and with a finite routing
+    bound and exponent cap that keep part of the quartets in FP64."""
     for m in (mol0, molecules.small_mixed()):
         ref = oracle_lib.grad(m)
-        for kw in ({}, {"mixed_tau64": math.inf, "mixed_p64": math.inf}):
+        for kw in ({"mixed_tau64": 0.1, "mixed_p64": 1000.0}, {"mixed_tau64": math.inf, "mixed_p64": math.inf}):
             p = tdg.Plan(m, schwarz_tol=0.0, precision=1, kernel_variant=variant, **kw)
             g, st = p.grad(m.P0, m.PD, m.R, stats=True)
             err = np.abs(g - ref).max()
             _say("mixed", variant, kw, "fp32 quartets", st["fp32_quartets"], "of", st["quartets"], "err", err)
             assert err <= MIXED_TOL
-            if kw and variant >= 0:  # fixed variants honour the routing exactly
+            if math.isinf(kw["mixed_tau64"]) and variant >= 0:  # fixed variants honour the routing
                 assert st["fp32_quartets"] == st["quartets"]
 
 
@@ -231,25 +232,28 @@ def test_mixed_all_fp64_routing_equals_fp64(tdg, mol0):
     assert np.abs(g1 - g2).max() <= 1e-12
 
 
-def test_chain60_mixed_against_stored_oracle(tdg):
+@pytest.mark.parametrize("tau64", [0.1, math.inf])
+def test_chain60_mixed_against_stored_oracle(tdg, tau64):
+    """Mixed path on the benchmark chain against the oracle's stored gradient, with the default
+    routing bound and with routing on class timing alone (the benchmark's setting)."""
     from paper_2407_16586_amd import synth
     ref = json.load(open(os.path.join(HERE, "golden", "chain60_tau1e-10.json")))
     m = synth.config1()
-    p = tdg.Plan(m, schwarz_tol=ref["tau"], precision=1)
+    p = tdg.Plan(m, schwarz_tol=ref["tau"], precision=1, mixed_tau64=tau64)
     g, st = p.grad(m.P0, m.PD, m.R, stats=True)
     err = np.abs(g - np.array(ref["grad"])).max()
-    _say("chain60 mixed max-abs", err, "fp32 fraction", st["fp32_quartets"] / st["quartets"])
+    _say("chain60 mixed", tau64, "max-abs", err, "fp32 fraction", st["fp32_quartets"] / st["quartets"])
     assert err <= MIXED_TOL
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_chain60_svp_against_stored_oracle(tdg, precision):
+@pytest.mark.parametrize("precision,tau64", [(0, 0.1), (1, 0.1), (1, math.inf)])
+def test_chain60_svp_against_stored_oracle(tdg, precision, tau64):
     """The same chain with def2-SVP-shaped exponent ranges (26.5M surviving quartets) against
     the oracle's stored gradient: FP64 within 1e-8, mixed within 1e-6."""
     from paper_2407_16586_amd import synth
     ref = json.load(open(os.path.join(HERE, "golden", "chain60svp_tau1e-10.json")))
     m = synth.config1("svp")
-    p = tdg.Plan(m, schwarz_tol=ref["tau"], precision=precision)
+    p = tdg.Plan(m, schwarz_tol=ref["tau"], precision=precision, mixed_tau64=tau64)
     g, st = p.grad(m.P0, m.PD, m.R, stats=True)
     err = np.abs(g - np.array(ref["grad"])).max()
     _say("chain60svp", precision, "max-abs", err, "quartets", st["quartets"], ref["oracle_stats"]["quartets"])
