@@ -13,6 +13,7 @@ struct DerivArgs {
     const int *pair_sa, *pair_sb, *pair_ppoff, *pair_npp; // sorted shell pairs
     const double *pp_p, *pp_Px, *pp_Py, *pp_Pz, *pp_c, *pp_za, *pp_zb; // primitive pairs
     const double *pp_ip;    // 1/p of each primitive pair
+    const double2 *pp_rec;  // per primitive pair, 4 x double2: (p, 1/p) (c, za) (zb, Px) (Py, Pz)
     const double *dens;     // shell-blocked P, D, R records with the angular normalisation folded in
     int n_bf;
     const int2 *tasks;      // (bra pair, ket pair) of this class
@@ -254,6 +255,10 @@ struct DerivClass {
     static constexpr int TPB = TPW * 4 < TPB_LDS ? TPW * 4 : TPB_LDS;
     static constexpr int WAVES = (TPB + TPW - 1) / TPW;
     static constexpr int BLOCK = WAVES * kWave;
+    // ket primitive records loaded one primitive ahead: pays where a primitive's work is
+    // short (few components, one root per lane); elsewhere the extra live registers
+    // would cost occupancy
+    static constexpr bool EARLY_PREFETCH = !ALLR && N <= 9;
 };
 
 // Shell-blocked densities: the record of the ordered shell pair (x, y) starts at
@@ -392,20 +397,31 @@ k_deriv(const DerivArgs a)
             const int pb0 = M.pair_ppoff[bra], nbp = M.pair_npp[bra];
             const int pk0 = M.pair_ppoff[ket], nkp = M.pair_npp[ket];
             const int gbase = (lane_ok ? team : 0) * K::GSTRIDE + set * N;
+            const double2 *rb = M.pp_rec + 4 * (size_t)pb0, *rk = M.pp_rec + 4 * (size_t)pk0;
             for (int ib = 0; ib < nbp; ++ib) {
-                const double p = M.pp_p[pb0 + ib], ip = M.pp_ip[pb0 + ib], zb2 = 2.0 * M.pp_zb[pb0 + ib];
+                const double2 b0 = rb[4 * ib], b1 = rb[4 * ib + 1], b2 = rb[4 * ib + 2], b3 = rb[4 * ib + 3];
+                const double p = b0.x, ip = b0.y, zab = b1.y, zb2 = 2.0 * b2.x;
                 // 2 pi^(5/2) times the bra contraction factor over p
-                const double cab = 34.98683665524972 * M.pp_c[pb0 + ib] * ip;
-                const double P[3] = {M.pp_Px[pb0 + ib], M.pp_Py[pb0 + ib], M.pp_Pz[pb0 + ib]};
+                const double cab = 34.98683665524972 * b1.x * ip;
+                const double P[3] = {b2.y, b3.x, b3.y};
+                // ket record of the current primitive; the next one is loaded ahead: at the
+                // start of the current primitive's work in the small classes (the latency of
+                // the load is then hidden behind the whole primitive), else at its end
+                double2 n0 = rk[0], n1 = rk[1], n2 = rk[2], n3 = rk[3];
                 for (int ik = 0; ik < nkp; ++ik) {
                     // Gamma is re-read from LDS for every primitive quartet: an opaque offset
                     // keeps the compiler from hoisting all N values into registers
                     int goff = gbase;
                     if constexpr (N > 8) asm volatile("" : "+v"(goff));
                     const F *gam = s_gam + goff;
-                    const double q = M.pp_p[pk0 + ik], iq = M.pp_ip[pk0 + ik], ccd = M.pp_c[pk0 + ik];
-                    const double zc2 = 2.0 * M.pp_za[pk0 + ik], zd2 = 2.0 * M.pp_zb[pk0 + ik];
-                    const double Q[3] = {M.pp_Px[pk0 + ik], M.pp_Py[pk0 + ik], M.pp_Pz[pk0 + ik]};
+                    const double2 k0 = n0, k1 = n1, k2 = n2, k3 = n3;
+                    const int kn = ik + 1 < nkp ? ik + 1 : ik;
+                    if constexpr (K::EARLY_PREFETCH) {
+                        n0 = rk[4 * kn]; n1 = rk[4 * kn + 1]; n2 = rk[4 * kn + 2]; n3 = rk[4 * kn + 3];
+                    }
+                    const double q = k0.x, iq = k0.y, ccd = k1.x;
+                    const double zc2 = 2.0 * k1.y, zd2 = 2.0 * k2.x;
+                    const double Q[3] = {k2.y, k3.x, k3.y};
                     const double sipq = rsq64(p + q), ipq = sipq * sipq;
                     const double rho = p * q * ipq;
                     double PQ[3], pq2 = 0.0;
@@ -477,7 +493,7 @@ k_deriv(const DerivArgs a)
                                     }
                     } else if constexpr (MODE == 1) {
                         constexpr int NBASE = (LA + 1) * (LB + 1) * (LC + 1) * (LD + 1);
-                        const double za = M.pp_za[pb0 + ib];
+                        const double za = zab;
                         const DirectCoef dc = direct_coef(za, 0.5 * zb2, 0.5 * zc2, 0.5 * zd2, p, q, ip, iq, u, ipq, B10, B01, B00);
                         F T[3][4 * NBASE];
 #pragma unroll
@@ -521,7 +537,7 @@ k_deriv(const DerivArgs a)
                         }
                     } else {
                         constexpr int NBASE = (LA + 1) * (LB + 1) * (LC + 1) * (LD + 1);
-                        const double za = M.pp_za[pb0 + ib];
+                        const double za = zab;
                         const DirectCoef dc = direct_coef(za, 0.5 * zb2, 0.5 * zc2, 0.5 * zd2, p, q, ip, iq, u, ipq, B10, B01, B00);
                         F I[3][NBASE], H[3][NBASE];
                         double CB[3], CCx[3], CDx[3];
@@ -570,6 +586,12 @@ k_deriv(const DerivArgs a)
 #pragma unroll
                     for (int k = 0; k < 9; ++k) acc[k] += double(pacc[k]);
                     } // roots of this lane
+                    if constexpr (!K::EARLY_PREFETCH) {
+                        // requested only after this primitive's contraction, so that the
+                        // record does not hold registers across the contraction
+                        asm volatile("" ::: "memory");
+                        n0 = rk[4 * kn]; n1 = rk[4 * kn + 1]; n2 = rk[4 * kn + 2]; n3 = rk[4 * kn + 3];
+                    }
                 }
             }
         }

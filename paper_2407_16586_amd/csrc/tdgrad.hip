@@ -132,6 +132,7 @@ struct tdg_plan {
     DevBuf<int> d_pair_sa, d_pair_sb, d_pair_ppoff, d_pair_npp, d_pair_K;
     DevBuf<double> d_pair_Q;
     DevBuf<double> d_pp_p, d_pp_Px, d_pp_Py, d_pp_Pz, d_pp_c, d_pp_za, d_pp_zb, d_pp_ip;
+    DevBuf<double> d_pp_rec; // the same eight values per primitive pair as one 64-byte record
     DevBuf<double> d_ang;                  // angular normalisation per AO
     DevBuf<int> d_grp_start;
     // work buffers
@@ -901,6 +902,17 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
         (rc = pl->d_pp_Pz.upload(pp[3])) || (rc = pl->d_pp_c.upload(pp[4])) || (rc = pl->d_pp_za.upload(pp[5])) ||
         (rc = pl->d_pp_zb.upload(pp[6])) || (rc = pl->d_pp_ip.upload(pp[7])))
         return rc;
+    {
+        // record layout read by the team kernels: p, 1/p, c, za, zb, Px, Py, Pz
+        const size_t npp = pp[0].size();
+        std::vector<double> rec(8 * npp);
+        for (size_t k = 0; k < npp; ++k) {
+            double *r = &rec[8 * k];
+            r[0] = pp[0][k]; r[1] = pp[7][k]; r[2] = pp[4][k]; r[3] = pp[5][k];
+            r[4] = pp[6][k]; r[5] = pp[1][k]; r[6] = pp[2][k]; r[7] = pp[3][k];
+        }
+        if ((rc = pl->d_pp_rec.upload(rec))) return rc;
+    }
     // screening items: (class, bra pair)
     pl->item_class_off.assign(kNumClasses + 1, 0);
     for (int c = 0; c < kNumClasses; ++c) {
@@ -999,8 +1011,8 @@ int tdg_plan_destroy(tdg_plan_t *pl)
     if (!pl) return TDG_OK;
     hipSetDevice(pl->device);
     DevBuf<double> *dbl[] = {&pl->d_coords, &pl->d_pair_Q, &pl->d_pp_p, &pl->d_pp_Px, &pl->d_pp_Py, &pl->d_pp_Pz,
-                             &pl->d_pp_c, &pl->d_pp_za, &pl->d_pp_zb, &pl->d_pp_ip, &pl->d_ang, &pl->d_in, &pl->d_dens,
-                             &pl->d_grad};
+                             &pl->d_pp_c, &pl->d_pp_za, &pl->d_pp_zb, &pl->d_pp_ip, &pl->d_pp_rec, &pl->d_ang, &pl->d_in,
+                             &pl->d_dens, &pl->d_grad};
     pl->d_bmax.release();
     for (auto *x : dbl) x->release();
     DevBuf<int> *ints[] = {&pl->d_shell_atom, &pl->d_shell_ao, &pl->d_shell_l, &pl->d_pair_sa, &pl->d_pair_sb,
@@ -1222,6 +1234,7 @@ static DerivArgs deriv_args(tdg_plan *pl)
     a.pair_npp = pl->d_pair_npp.p;
     a.pp_p = pl->d_pp_p.p; a.pp_Px = pl->d_pp_Px.p; a.pp_Py = pl->d_pp_Py.p; a.pp_Pz = pl->d_pp_Pz.p;
     a.pp_c = pl->d_pp_c.p; a.pp_za = pl->d_pp_za.p; a.pp_zb = pl->d_pp_zb.p; a.pp_ip = pl->d_pp_ip.p;
+    a.pp_rec = reinterpret_cast<const double2 *>(pl->d_pp_rec.p);
     a.dens = pl->d_dens.p; a.n_bf = pl->n_bf;
     a.omega = pl->prm.omega; a.alpha = pl->prm.alpha; a.beta = pl->prm.beta; a.terms = pl->prm.terms;
     a.grad = pl->d_grad.p; a.n_atoms = pl->n_atoms;
