@@ -35,6 +35,7 @@ struct WaveClass {
     static constexpr int WAVES = WAVE_LDS * FB * 4 <= 64 * 1024 ? 4 : 2;
     static constexpr int BLOCK = WAVES * kWave;
     static constexpr int CPL = (N + kWave - 1) / kWave;  // components per lane
+    static constexpr bool EARLY_PREFETCH = N <= 27;      // next ket record loaded ahead
 };
 
 template <int LA, int LB, int LC, int LD, bool LR, typename F, bool BATCH>
@@ -107,17 +108,37 @@ k_deriv_wave(const DerivArgs a)
         for (int k = 0; k < 9; ++k) acc[k] = 0.0;
         const int pb0 = M.pair_ppoff[bra], nbp = M.pair_npp[bra];
         const int pk0 = M.pair_ppoff[ket], nkp = M.pair_npp[ket];
+        // primitive-pair records (p, 1/p) (c, za) (zb, P); in the classes with few
+        // components the ket record of the next primitive quartet is requested while the
+        // current one is evaluated (elsewhere the extra live registers cost occupancy)
+        const double2 *rb = M.pp_rec + 4 * (size_t)pb0, *rk = M.pp_rec + 4 * (size_t)pk0;
+        double2 n0, n1, n2, n3, c0, c1, c2, c3;
+        if constexpr (K::EARLY_PREFETCH) {
+            n0 = rk[0]; n1 = rk[1]; n2 = rk[2]; n3 = rk[3];
+        }
         for (int ib = 0; ib < nbp; ++ib) {
             for (int ik = 0; ik < nkp; ++ik) {
+                if constexpr (K::EARLY_PREFETCH) {
+                    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+                    const int kn = ik + 1 < nkp ? ik + 1 : 0;
+                    n0 = rk[4 * kn]; n1 = rk[4 * kn + 1]; n2 = rk[4 * kn + 2]; n3 = rk[4 * kn + 3];
+                }
                 for (int ch = 0; ch < NCHUNK; ++ch) {
                     const int slot = ch * CH + s1;
                     if (s1 < CH && slot < NSLOT) {
-                        const double p = M.pp_p[pb0 + ib], ip = M.pp_ip[pb0 + ib], cab = M.pp_c[pb0 + ib];
-                        const double zb2 = 2.0 * M.pp_zb[pb0 + ib];
-                        const double q = M.pp_p[pk0 + ik], iq = M.pp_ip[pk0 + ik], ccd = M.pp_c[pk0 + ik];
-                        const double zc2 = 2.0 * M.pp_za[pk0 + ik], zd2 = 2.0 * M.pp_zb[pk0 + ik];
-                        const double P[3] = {M.pp_Px[pb0 + ib], M.pp_Py[pb0 + ib], M.pp_Pz[pb0 + ib]};
-                        const double Q[3] = {M.pp_Px[pk0 + ik], M.pp_Py[pk0 + ik], M.pp_Pz[pk0 + ik]};
+                        const double2 b0 = rb[4 * ib], b1 = rb[4 * ib + 1], b2 = rb[4 * ib + 2], b3 = rb[4 * ib + 3];
+                        double2 k0, k1, k2, k3;
+                        if constexpr (K::EARLY_PREFETCH) {
+                            k0 = c0; k1 = c1; k2 = c2; k3 = c3;
+                        } else {
+                            k0 = rk[4 * ik]; k1 = rk[4 * ik + 1]; k2 = rk[4 * ik + 2]; k3 = rk[4 * ik + 3];
+                        }
+                        const double p = b0.x, ip = b0.y, cab = b1.x;
+                        const double zb2 = 2.0 * b2.x;
+                        const double q = k0.x, iq = k0.y, ccd = k1.x;
+                        const double zc2 = 2.0 * k1.y, zd2 = 2.0 * k2.x;
+                        const double P[3] = {b2.y, b3.x, b3.y};
+                        const double Q[3] = {k2.y, k3.x, k3.y};
                         const double sipq = rsq64(p + q), ipq = sipq * sipq, rho = p * q * ipq;
                         const double PQ0 = P[0] - Q[0], PQ1 = P[1] - Q[1], PQ2 = P[2] - Q[2];
                         const double pq2 = PQ0 * PQ0 + PQ1 * PQ1 + PQ2 * PQ2;
@@ -140,7 +161,7 @@ k_deriv_wave(const DerivArgs a)
                         const double B01 = 0.5 * iq * (1.0 - p * ipq * u);
                         const double PQd = d1 == 0 ? PQ0 : (d1 == 1 ? PQ1 : PQ2);
                         const double Pd = P[d1 == 0 ? 0 : (d1 == 1 ? 1 : 2)], Qd = Q[d1 == 0 ? 0 : (d1 == 1 ? 1 : 2)];
-                        const double za = M.pp_za[pb0 + ib];
+                        const double za = b1.y;
                         const DirectCoef dc =
                             direct_coef(za, 0.5 * zb2, 0.5 * zc2, 0.5 * zd2, p, q, ip, iq, u, ipq, B10, B01, B00);
                         const double CA = (Pd - Ad) - q * ipq * u * PQd, CB = CA + ABd;

@@ -1500,10 +1500,10 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             a.batch = lead->d_bargs.p;
             a.lds_atoms = 0; // gradients of many molecules: direct FP64 atomics
         }
-        auto set_range = [&](DerivArgs &x, int c, int pr) {
-            x.tasks = tasks + ch.seg_begin[c][pr];
-            x.task_mol = task_mol ? task_mol + ch.seg_begin[c][pr] : nullptr;
-            x.ntasks = ch.seg_end[c][pr] - ch.seg_begin[c][pr];
+        auto set_span = [&](DerivArgs &x, long long b, long long e) {
+            x.tasks = tasks + b;
+            x.task_mol = task_mol ? task_mol + b : nullptr;
+            x.ntasks = e - b;
         };
         bool need_tune = false;
         for (int c = 0; c < kNumClasses; ++c)
@@ -1547,15 +1547,15 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                     if (v == 0 && !lead->tf_ok[pr][0][c]) continue;
                     if (v == 3 && !lead->tf_ok[pr][1][c]) continue;
                     float ms = 1e30f;
+                    // adjacent ranges run as one launch, as in the timed call
+                    const bool merge = e0 > b0 && e1 > b1 && e0 == b1;
                     for (int rep = 0; rep < 3; ++rep) { // a warm-up round, then the faster of two
                         float t = 0.f;
                         HIP_TRY(hipEventRecord(lead->ev_cls[0], st));
-                        for (int k = 0; k < 2; ++k) {
-                            const long long b = k ? b1 : b0, e = k ? e1 : e0;
+                        for (int k = 0; k < (merge ? 1 : 2); ++k) {
+                            const long long b = k ? b1 : b0, e = merge ? e1 : (k ? e1 : e0);
                             if (e <= b) continue;
-                            at.tasks = tasks + b;
-                            at.task_mol = task_mol ? task_mol + b : nullptr;
-                            at.ntasks = e - b;
+                            set_span(at, b, e);
                             HIP_TRY(kLaunch[c](v, pr, at, lr, st, grid_max));
                         }
                         HIP_TRY(hipEventRecord(lead->ev_cls[1], st));
@@ -1594,13 +1594,21 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
         HIP_TRY(hipEventRecord(lead->ev0, st));
         for (int c = 0; c < kNumClasses; ++c) {
             HIP_TRY(hipEventRecord(lead->ev_cls[c], st));
-            // each segment is launched on its own (a class that is not split runs its
-            // FP32-routed segment with the FP64 kernel)
-            for (int pr = 0; pr < 2; ++pr) {
-                set_range(a, c, pr);
-                if (!a.ntasks) continue;
-                const int prec = split[c] ? pr : 0;
-                HIP_TRY(kLaunch[c](variant[prec][c], prec, a, lr, st, grid_max));
+            // a class that is not split runs its FP32-routed segment with the FP64 kernel:
+            // one launch when the two segments are adjacent, else one per segment (the
+            // learned veto compacts each segment in place)
+            const long long b0 = ch.seg_begin[c][0], e0 = ch.seg_end[c][0];
+            const long long b1 = ch.seg_begin[c][1], e1 = ch.seg_end[c][1];
+            if (!split[c] && e0 == b1) {
+                set_span(a, b0, e1);
+                if (a.ntasks) HIP_TRY(kLaunch[c](variant[0][c], 0, a, lr, st, grid_max));
+            } else {
+                for (int pr = 0; pr < 2; ++pr) {
+                    set_span(a, ch.seg_begin[c][pr], ch.seg_end[c][pr]);
+                    if (!a.ntasks) continue;
+                    const int prec = split[c] ? pr : 0;
+                    HIP_TRY(kLaunch[c](variant[prec][c], prec, a, lr, st, grid_max));
+                }
             }
         }
         HIP_TRY(hipEventRecord(lead->ev_cls[kNumClasses], st));
