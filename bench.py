@@ -224,6 +224,7 @@ def main():
                                    else args.mixed_tau64) if use_mixed else None},
         "wall_s": head["ms_step"] * 1e-3,
         "quartets": head["quartets"],
+        "screened_candidates": st["candidates"],
         "prim_quartets": st["prim_quartets"],
         "kernel_ms": float(head["class_ms"].sum()),
         "kernel_quartets_per_s": head["quartets"] / (head["class_ms"].sum() * 1e-3),

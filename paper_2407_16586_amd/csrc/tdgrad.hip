@@ -1,14 +1,14 @@
 // tdgrad.hip -- host runtime, set-up kernels and C ABI of libtdgrad.so.
 //
 // Pipeline of one gradient call (all on the caller's stream):
-//   a3 density preparation: angular normalisation folded into P0, D = P0 + 2 PDelta
+//   density preparation: angular normalisation folded into P0, D = P0 + 2 PDelta
 //      and R; shell-block maxima of |P0|, |D|, |R| for the screening bound;
-//   a4 task generation: for each of the 21 angular classes and each bra pair, the
+//   task generation: for each of the 21 angular classes and each bra pair, the
 //      ket pairs whose density-multiplied Schwarz bound passes (section II.E),
 //      found as a Q-sorted prefix per contraction group, then tested exactly;
-//   a5-a10 one class kernel per class (deriv_kernel.hpp), accumulating into the
-//      per-atom FP64 gradient.
-// The plan (tdg_plan_create) holds a1-a2: normalisation, shell pairs, primitive
+//   class kernels: one per class (deriv_kernel.hpp, deriv_wave.hpp), accumulating
+//      into the per-atom FP64 gradient.
+// The plan (tdg_plan_create) holds the normalisation, shell pairs, primitive
 // pairs and Schwarz factors, sorted by class, contraction degree and Q (D1 of
 // section II.C: presorted shell-pair lists).
 #include <hip/hip_runtime.h>
@@ -169,7 +169,7 @@ struct tdg_plan {
     int bvariant[2][kNumClasses];
     int bsplit[kNumClasses];
     bool btuned[kNumClasses] = {};
-    // learned screening (a13): estimator and thresholds (log10 of the contribution)
+    // learned screening: estimator and thresholds (log10 of the contribution)
     const tdg_mlp *ml = nullptr;
     double ml_log10 = -1e30, ml_tau_hi = 0.0;
     std::vector<double> pair_pmin;
@@ -192,7 +192,7 @@ struct tdg_plan {
     std::vector<unsigned long long> h_prim, h_cand;
 };
 
-// ======================================================================= a1
+// ======================================================================= normalisation
 static double dfact(int n)
 {
     double r = 1.0;
@@ -221,7 +221,7 @@ static double ang_factor(int lx, int ly, int lz)
     return std::sqrt(dfact(2 * l - 1) / (dfact(2 * lx - 1) * dfact(2 * ly - 1) * dfact(2 * lz - 1)));
 }
 
-// ======================================================================= a2: Schwarz
+// ======================================================================= shell pairs and Schwarz factors
 // Q_ab = sqrt(max over components (mu nu|mu nu)), (ab|ab) by Rys quadrature with
 // LA+LB+1 roots, one thread per pair.
 template <int LA, int LB>
@@ -288,7 +288,7 @@ __global__ void k_schwarz(int npair, const int *pair_sa, const int *pair_sb, con
     Q[i] = sqrt(mx);
 }
 
-// ======================================================================= a3
+// ======================================================================= density preparation
 // scaled densities and shell-block maxima; one thread per shell block (a, c)
 // max over the block products that Gamma contains (reading R10), times Q_ab Q_cd;
 // ab is the bra pair's record (uniform across a wavefront)
@@ -341,7 +341,7 @@ __global__ void k_density_prep(int n_shells, int n_bf, const int *shell_l, const
     atomicMax(mx, (unsigned long long)__double_as_longlong(m)); // non-negative doubles order as integers
 }
 
-// ======================================================================= a4
+// ======================================================================= screening and task generation
 struct ScreenArgs {
     int cls, pb, pk;
     int bra0, nbra;               // bra pairs of this class: sorted indices [bra0, bra0+nbra)
@@ -381,14 +381,41 @@ struct ScreenArgs {
 // stored masks.  In the mixed-precision mode a survivor goes to the FP32 list
 // when its bound times the two pairs' proxies is < tau64 and no primitive exponent
 // sum reaches p64; otherwise to the FP64 list.
+//
+// All classes (of one molecule) are screened by one launch: the per-class fields travel in
+// a table in the kernel arguments, wavefronts [wave_start[k], wave_start[k+1]) serve item k.
+struct ScreenItem {
+    int cls, pb, pk, bra0, nbra, grp0, grp1, item_base, bgrp0, bgrp1, fgrp_base;
+};
+struct ScreenTable {
+    int n;
+    int wave_start[kNumClasses + 1];
+    ScreenItem it[kNumClasses];
+};
+
 template <int MODE>
-__global__ void __launch_bounds__(256) k_screen(const ScreenArgs s)
+__global__ void __launch_bounds__(256) k_screen(ScreenArgs s, const ScreenTable t)
 {
     constexpr int MAXCH = 96; // chunks whose masks a wavefront keeps in LDS (MODE 2)
     __shared__ unsigned long long s_mask[MODE == 2 ? 4 : 1][MODE == 2 ? MAXCH : 1][2];
-    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+    const int gw = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave));
+    const int lane = threadIdx.x % kWave;
     const int wv = (threadIdx.x / kWave) & 3;
-    if (wid >= s.nbra) return;
+    if (gw >= t.wave_start[t.n]) return;
+    int ci = 0;
+    while (ci + 1 < t.n && t.wave_start[ci + 1] <= gw) ++ci;
+    {
+        const ScreenItem &it = t.it[ci];
+        s.cls = it.cls; s.pb = it.pb; s.pk = it.pk; s.bra0 = it.bra0; s.nbra = it.nbra;
+        s.grp0 = it.grp0; s.grp1 = it.grp1; s.bgrp0 = it.bgrp0; s.bgrp1 = it.bgrp1;
+        if constexpr (MODE == 2) {
+            s.ccnt += 2 * it.fgrp_base; s.freg += 2 * it.fgrp_base; s.fcap += 2 * it.fgrp_base;
+        } else {
+            s.item_cnt += it.item_base; s.item_off += it.item_base;
+            s.item_cnt32 += it.item_base; s.item_off32 += it.item_base;
+        }
+    }
+    const int wid = gw - t.wave_start[ci];
     const int i = s.bra0 + wid;
     const int a = s.pair_sa[i], b = s.pair_sb[i];
     const double Qi = s.pair_Q[i];
@@ -516,7 +543,9 @@ __global__ void k_zero(double *p, long long n)
 }
 
 // fused screening: copy the used part of every region to its place in the packed list;
-// one block per region, moves[3 r] = (source, destination, count)
+// one block per piece of a region, moves[3 r] = (source, destination, count)
+constexpr long long kPackPiece = 4096; // tasks per piece
+
 __global__ void k_pack_regions(const int2 *src, int2 *dst, const long long *moves)
 {
     const long long from = moves[3 * blockIdx.x], to = moves[3 * blockIdx.x + 1], n = moves[3 * blockIdx.x + 2];
@@ -524,7 +553,7 @@ __global__ void k_pack_regions(const int2 *src, int2 *dst, const long long *move
 }
 
 // ======================================================================= dispatch
-// ======================================================================= a13
+// ======================================================================= learned screening
 // Features of a shell quartet for the contribution estimator (10 used of 16):
 //   log10 Q_ab, log10 Q_cd, log10 of the largest density-block product (all /10),
 //   log10 of the smallest and largest primitive exponent sums of both pairs (/4),
@@ -716,7 +745,7 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
     for (int s = 0; s < ns; ++s) nbf = std::max(nbf, b->shell_ao_off[s] + ncart(b->shell_l[s]));
     pl->n_bf = nbf;
 
-    // a1: normalised coefficients and per-AO angular factors
+    // normalised coefficients and per-AO angular factors
     std::vector<double> coef(b->n_prims);
     for (int s = 0; s < ns; ++s)
         normalise(b->shell_l[s], b->shell_nprim[s], b->exps + b->shell_prim_off[s], b->coefs + b->shell_prim_off[s],
@@ -728,7 +757,7 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
             ang[b->shell_ao_off[s] + k] = ang_factor(t[0], t[1], t[2]);
         }
 
-    // a2: canonical pairs (first shell has the higher l; equal l: higher index first)
+    // canonical pairs (first shell has the higher l; equal l: higher index first)
     struct PairRec { int sa, sb, cls, K; long long user; };
     std::vector<PairRec> pr;
     pr.reserve((size_t)ns * (ns + 1) / 2);
@@ -1069,22 +1098,33 @@ int tdg_plan_schwarz(const tdg_plan_t *pl, double *Q)
 } // extern "C"
 
 // --------------------------------------------------------------------------
-// One or several molecules: per molecule a3 and the a4 count pass; one host
-// synchronisation for the task counts; the a4 fill pass into one task list laid
+// One or several molecules: per molecule the density preparation and the screening
+// count pass; one host synchronisation for the task counts; the fill pass into one task list laid
 // out per (class, precision) with the molecules concatenated; one launch per
-// (class, precision) over all molecules (a5-a10).
+// (class, precision) over all molecules (the class kernels).
 
-static void screen_setup(tdg_plan *pl, ScreenArgs &s, int c)
+// screening item of class c over its bras [skip, skip + nbra) (nbra < 0: all)
+static void screen_add(tdg_plan *pl, ScreenTable &t, int c, int skip = 0, int nbra = -1)
 {
     int pb, pk;
     class_pk(c, pb, pk);
-    s.cls = c; s.pb = pb; s.pk = pk;
-    s.bra0 = pl->pc_start[pb]; s.nbra = pl->pc_start[pb + 1] - pl->pc_start[pb];
-    s.grp0 = pl->pc_grp_start[pk]; s.grp1 = pl->pc_grp_start[pk + 1];
-    s.item_cnt = pl->d_item_cnt.p + pl->item_class_off[c];
-    s.item_off = pl->d_item_off.p + pl->item_class_off[c];
-    s.item_cnt32 = pl->d_item_cnt32.p + pl->item_class_off[c];
-    s.item_off32 = pl->d_item_off32.p + pl->item_class_off[c];
+    ScreenItem &it = t.it[t.n];
+    it.cls = c; it.pb = pb; it.pk = pk;
+    it.bra0 = pl->pc_start[pb] + skip;
+    it.nbra = nbra >= 0 ? nbra : pl->pc_start[pb + 1] - pl->pc_start[pb] - skip;
+    it.grp0 = pl->pc_grp_start[pk]; it.grp1 = pl->pc_grp_start[pk + 1];
+    it.item_base = pl->item_class_off[c] + skip;
+    it.bgrp0 = pl->pc_grp_start[pb]; it.bgrp1 = pl->pc_grp_start[pb + 1];
+    it.fgrp_base = pl->fgrp_off.empty() ? 0 : pl->fgrp_off[c];
+    if (it.nbra <= 0) return;
+    t.wave_start[t.n + 1] = t.wave_start[t.n] + it.nbra;
+    ++t.n;
+}
+
+template <int MODE>
+static void screen_launch(const ScreenArgs &s, const ScreenTable &t, hipStream_t st)
+{
+    if (t.n) hipLaunchKernelGGL(k_screen<MODE>, dim3((t.wave_start[t.n] + 3) / 4), dim3(256), 0, st, s, t);
 }
 
 static ScreenArgs screen_args(tdg_plan *pl)
@@ -1099,6 +1139,8 @@ static ScreenArgs screen_args(tdg_plan *pl)
     s.tau64 = pl->prm.mixed_tau64; s.p64 = pl->prm.mixed_p64;
     s.pair_pmax = pl->d_pair_pmax.p; s.pair_famp = pl->d_pair_famp.p;
     s.prim_cnt = pl->d_prim_cnt.p; s.cand_cnt = pl->d_cand_cnt.p;
+    s.item_cnt = pl->d_item_cnt.p; s.item_off = pl->d_item_off.p;
+    s.item_cnt32 = pl->d_item_cnt32.p; s.item_off32 = pl->d_item_off32.p;
     return s;
 }
 
@@ -1109,7 +1151,7 @@ static bool class_active(tdg_plan *pl, int c)
     return pl->pc_start[pb + 1] > pl->pc_start[pb] && pl->pc_grp_start[pk + 1] > pl->pc_grp_start[pk];
 }
 
-// a3 for one molecule (asynchronous): density records, block maxima, zeroed counters
+// density preparation for one molecule (asynchronous): density records, block maxima, zeroed counters
 static int prep_density(tdg_plan *pl, const double *P0, const double *PD, const double *R, int ptr_kind,
                           hipStream_t st)
 {
@@ -1139,15 +1181,14 @@ static int prep_density(tdg_plan *pl, const double *P0, const double *PD, const 
     return TDG_OK;
 }
 
-// count pass of a4 for one molecule (asynchronous); counts copied to host buffers
+// screening count pass for one molecule (asynchronous); counts copied to host buffers
 static int count_pass(tdg_plan *pl, hipStream_t st)
 {
     ScreenArgs s = screen_args(pl);
-    for (int c = 0; c < kNumClasses; ++c) {
-        if (!class_active(pl, c)) continue;
-        screen_setup(pl, s, c);
-        hipLaunchKernelGGL(k_screen<0>, dim3((s.nbra + 3) / 4), dim3(256), 0, st, s);
-    }
+    ScreenTable t{};
+    for (int c = 0; c < kNumClasses; ++c)
+        if (class_active(pl, c)) screen_add(pl, t, c);
+    screen_launch<0>(s, t, st);
     HIP_TRY(hipGetLastError());
     const int nitems = pl->item_class_off[kNumClasses];
     pl->h_cnt.assign(nitems, 0);
@@ -1172,7 +1213,7 @@ static FeatArgs feat_args(tdg_plan *pl)
     return f;
 }
 
-// a13 veto on the screened task list of one molecule: each (class, precision) segment is
+// learned-screening veto on the screened task list of one molecule: each (class, precision) segment is
 // filtered by the estimator and compacted (order kept) into the second task buffer;
 // segment ends are updated (one host synchronisation)
 static int ml_filter(tdg_plan *pl, int2 *&tasks, long long (*seg_begin)[2], long long (*seg_end)[2], hipStream_t st,
@@ -1249,7 +1290,7 @@ struct Chunk {
     long long total = 0;
 };
 
-// a4 in one launch per class (k_screen<2>) into regions sized from the previous call,
+// screening of all classes in one launch (k_screen<2>) into regions sized from the previous call,
 // then the used part of every region packed into one list per (class, list) in class order;
 // ok = false when a region overflowed (the caller then runs the count and fill passes).
 // The counts per region are left in pl->hcnt.
@@ -1269,18 +1310,13 @@ static int fused_screen(tdg_plan *pl, hipStream_t st, Chunk &ch, int2 *&tasks, b
     hipLaunchKernelGGL(k_zero, dim3((nflat + 255) / 256 + 1), dim3(256), 0, st, (double *)pl->d_ccnt.p, (long long)nflat);
     ScreenArgs s = screen_args(pl);
     s.tasks = pl->d_tasks.p;
-    for (int c = 0; c < kNumClasses; ++c) {
-        if (!class_active(pl, c)) continue;
-        screen_setup(pl, s, c);
-        int pb, pk;
-        class_pk(c, pb, pk);
-        s.bgrp0 = pl->pc_grp_start[pb];
-        s.bgrp1 = pl->pc_grp_start[pb + 1];
-        s.ccnt = pl->d_ccnt.p + 2 * pl->fgrp_off[c];
-        s.freg = pl->d_freg.p + 2 * pl->fgrp_off[c];
-        s.fcap = pl->d_fcap.p + 2 * pl->fgrp_off[c];
-        hipLaunchKernelGGL(k_screen<2>, dim3((s.nbra + 3) / 4), dim3(256), 0, st, s);
-    }
+    s.ccnt = pl->d_ccnt.p;
+    s.freg = pl->d_freg.p;
+    s.fcap = pl->d_fcap.p;
+    ScreenTable t{};
+    for (int c = 0; c < kNumClasses; ++c)
+        if (class_active(pl, c)) screen_add(pl, t, c);
+    screen_launch<2>(s, t, st);
     HIP_TRY(hipGetLastError());
     std::vector<unsigned long long> cnt(nflat);
     pl->h_prim.assign(kNumClasses, 0);
@@ -1304,10 +1340,13 @@ static int fused_screen(tdg_plan *pl, hipStream_t st, Chunk &ch, int2 *&tasks, b
             ch.seg_begin[c][pr] = pos;
             for (int g = pl->fgrp_off[c]; g < pl->fgrp_off[c + 1]; ++g) {
                 const long long n = pl->hcnt[2 * g + pr];
-                if (!n) continue;
-                moves.push_back(pl->freg[2 * g + pr]);
-                moves.push_back(pos);
-                moves.push_back(n);
+                // one block per piece of at most kPackPiece tasks, so that large regions
+                // are copied by many blocks
+                for (long long k = 0; k < n; k += kPackPiece) {
+                    moves.push_back(pl->freg[2 * g + pr] + k);
+                    moves.push_back(pos + k);
+                    moves.push_back(std::min(kPackPiece, n - k));
+                }
                 pos += n;
             }
             ch.seg_end[c][pr] = pos;
@@ -1363,7 +1402,7 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
     HIP_TRY(hipSetDevice(lead->device));
     int rc;
     const bool batched = n > 1;
-    // a4: one fused launch per class when the previous call sized the regions, else (and
+    // screening: one fused launch when the previous call sized the regions, else (and
     // after an overflow) the count pass, per-item offsets on the host and the fill pass
     bool fused = false;
     Chunk fch;
@@ -1471,17 +1510,14 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             s.tasks = tasks;
             s.task_mol = task_mol;
             s.mol = m;
+            ScreenTable t{};
             for (int c = 0; c < kNumClasses; ++c) {
                 if (!class_active(pl, c)) continue;
-                screen_setup(pl, s, c);
                 const int lo = std::max(pl->item_class_off[c], i0), hi = std::min(pl->item_class_off[c + 1], i1);
                 if (hi <= lo) continue;
-                const int skip = lo - pl->item_class_off[c];
-                s.bra0 += skip;
-                s.nbra = hi - lo;
-                s.item_cnt += skip; s.item_off += skip; s.item_cnt32 += skip; s.item_off32 += skip;
-                hipLaunchKernelGGL(k_screen<1>, dim3((s.nbra + 3) / 4), dim3(256), 0, st, s);
+                screen_add(pl, t, c, lo - pl->item_class_off[c], hi - lo);
             }
+            screen_launch<1>(s, t, st);
         }
         HIP_TRY(hipGetLastError());
         } // two-pass task generation
@@ -1490,7 +1526,7 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             if ((rc = ml_filter(lead, tasks, ch.seg_begin, ch.seg_end, st, sk))) return rc;
             ml_skipped += sk;
         }
-        // a5-a10
+        // class kernels
         DerivArgs a = deriv_args(lead);
         if (batched) {
             std::vector<DerivArgs> margs(n);
@@ -1509,7 +1545,7 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
         for (int c = 0; c < kNumClasses; ++c)
             need_tune |= !tuned[c] && ch.seg_end[c][1] > ch.seg_begin[c][0];
         if (lead->prm.autotune && lead->prm.kernel_variant < 0 && need_tune) {
-            // a12 autotuner: time the kernel variants of each class on this call's task list
+            // autotuner: time the kernel variants of each class on this call's task list
             // (into scratch gradients) and keep the fastest for later calls.  The wavefront
             // design is a candidate for classes with >= 27 components, the two team designs
             // for every class.  With the mixed route
@@ -1736,11 +1772,10 @@ int tdg_collect(tdg_plan_t *pl, const double *P0, const double *PD, const double
         HIP_TRY(hipMemcpyAsync(pl->d_item_off.p, offs.data(), 8 * offs.size(), hipMemcpyHostToDevice, st));
     ScreenArgs s = screen_args(pl);
     s.tasks = pl->d_tasks.p;
-    for (int c = 0; c < kNumClasses; ++c) {
-        if (!class_active(pl, c)) continue;
-        screen_setup(pl, s, c);
-        hipLaunchKernelGGL(k_screen<1>, dim3((s.nbra + 3) / 4), dim3(256), 0, st, s);
-    }
+    ScreenTable t{};
+    for (int c = 0; c < kNumClasses; ++c)
+        if (class_active(pl, c)) screen_add(pl, t, c);
+    screen_launch<1>(s, t, st);
     DevBuf<double> contrib;
     if ((rc = contrib.alloc(std::max<long long>(12 * total, 1)))) return rc;
     hipLaunchKernelGGL(k_zero, dim3((unsigned)((12 * total + 255) / 256 + 1)), dim3(256), 0, st, contrib.p, 12 * total);
