@@ -356,11 +356,35 @@ k_deriv(const DerivArgs a)
     }
     const double iom2 = LR ? 1.0 / (a.omega * a.omega) : 0.0;
     const long long stride = (long long)gridDim.x * TPB;
+    // batched launches: the LDS array holds the gradient of molecule cur (the molecule of
+    // the block's first task); it is flushed when the block moves on to another molecule
+    // (tasks are molecule-major within a class, so that is rare), and tasks of other
+    // molecules inside a block's range go straight to their global gradient
+    int cur = -1;
+    auto flush_mol = [&](int m) {
+        const int n3 = 3 * a.batch[m].n_atoms;
+        double *g = a.batch[m].grad;
+        for (int i = tid; i < n3; i += blockDim.x) {
+            const double v = s_atoms[i];
+            if (v != 0.0) atomic_add_global(&g[i], v);
+            s_atoms[i] = 0.0;
+        }
+    };
     for (long long base = (long long)blockIdx.x * TPB; base < a.ntasks; base += stride) {
+        if constexpr (BATCH) {
+            const int m0 = a.task_mol[base];
+            if (a.lds_atoms && m0 != cur) { // block-uniform
+                __syncthreads();
+                if (cur >= 0) flush_mol(cur);
+                __syncthreads();
+                cur = m0;
+            }
+        }
         const long long t = base + team;
         const bool valid = lane_ok && t < a.ntasks;
         int bra = 0, ket = 0, sa = 0, sb = 0, sc = 0, sd = 0;
-        const DerivArgs &M = BATCH ? a.batch[valid ? a.task_mol[t] : 0] : a;
+        const int tmol = BATCH && valid ? a.task_mol[t] : 0;
+        const DerivArgs &M = BATCH ? a.batch[tmol] : a;
         if (valid) {
             const int2 tk = a.tasks[t];
             bra = tk.x;
@@ -613,7 +637,7 @@ k_deriv(const DerivArgs a)
                 for (int X = 0; X < 4; ++X)
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
-                        if (a.lds_atoms) atomicAdd(&s_atoms[3 * at[X] + d], out[3 * X + d]);
+                        if (a.lds_atoms && (!BATCH || tmol == cur)) atomicAdd(&s_atoms[3 * at[X] + d], out[3 * X + d]);
                         else atomic_add_global(&M.grad[3 * at[X] + d], out[3 * X + d]);
                     }
             }
@@ -622,9 +646,13 @@ k_deriv(const DerivArgs a)
     }
     if (a.lds_atoms) {
         __syncthreads();
-        for (int i = tid; i < 3 * a.n_atoms; i += blockDim.x) {
-            const double v = s_atoms[i];
-            if (v != 0.0) atomic_add_global(&a.grad[i], v);
+        if constexpr (BATCH) {
+            if (cur >= 0) flush_mol(cur);
+        } else {
+            for (int i = tid; i < 3 * a.n_atoms; i += blockDim.x) {
+                const double v = s_atoms[i];
+                if (v != 0.0) atomic_add_global(&a.grad[i], v);
+            }
         }
     }
 }

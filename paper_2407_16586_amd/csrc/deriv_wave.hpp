@@ -50,7 +50,10 @@ k_deriv_wave(const DerivArgs a)
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     F *tab = s_tab + wave * K::WAVE_LDS;
-    if (a.lds_atoms) {
+    // block-level accumulation in LDS for one molecule; a batched launch adds each
+    // quartet's 12 values to its molecule's global gradient
+    const bool use_lds = a.lds_atoms && !BATCH;
+    if (use_lds) {
         for (int i = tid; i < 3 * a.n_atoms; i += blockDim.x) s_atoms[i] = 0.0;
         __syncthreads();
     }
@@ -220,11 +223,11 @@ k_deriv_wave(const DerivArgs a)
             const double v = X == 0 ? -(acc[d] + acc[3 + d] + acc[6 + d]) : acc[3 * (X - 1) + d];
             const int at = X == 0 ? atA : (X == 1 ? atB : (X == 2 ? atC : atD));
             if (a.task_out) atomic_add_global(&a.task_out[12 * t + lane], v);
-            else if (a.lds_atoms) atomicAdd(&s_atoms[3 * at + d], v);
+            else if (use_lds) atomicAdd(&s_atoms[3 * at + d], v);
             else atomic_add_global(&M.grad[3 * at + d], v);
         }
     }
-    if (a.lds_atoms) {
+    if (use_lds) {
         __syncthreads();
         for (int i = tid; i < 3 * a.n_atoms; i += blockDim.x) {
             const double v = s_atoms[i];

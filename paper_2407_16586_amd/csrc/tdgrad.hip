@@ -162,6 +162,8 @@ struct tdg_plan {
     DevBuf<long long> d_item_off32;
     bool tuned[kNumClasses] = {};          // variants of the class measured (on the first chunk holding it)
     DevBuf<double> d_grad_tune;            // scratch gradient for the tuning launches
+    DevBuf<int2> d_tune_tasks;             // strided sample of a class's tasks for the autotuner
+    DevBuf<int> d_tune_mol;
     // buffers of batched calls led by this plan (the first plan of tdg_grad_jk_batch)
     DevBuf<int2> d_btasks;
     DevBuf<int> d_bmol;
@@ -536,6 +538,16 @@ __global__ void __launch_bounds__(256) k_screen(ScreenArgs s, const ScreenTable 
     }
 }
 
+// autotuner sample of a task range: every stride-th task (and its molecule index)
+__global__ void k_sample_tasks(const int2 *src, const int *src_mol, long long b, long long stride, long long n,
+                               int2 *dst, int *dst_mol)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dst[i] = src[b + i * stride];
+    if (src_mol) dst_mol[i] = src_mol[b + i * stride];
+}
+
 __global__ void k_zero(double *p, long long n)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -545,6 +557,7 @@ __global__ void k_zero(double *p, long long n)
 // fused screening: copy the used part of every region to its place in the packed list;
 // one block per piece of a region, moves[3 r] = (source, destination, count)
 constexpr long long kPackPiece = 4096; // tasks per piece
+constexpr long long kTuneTasks = 1LL << 19; // tasks per class the autotuner times at most
 
 __global__ void k_pack_regions(const int2 *src, int2 *dst, const long long *moves)
 {
@@ -1051,6 +1064,8 @@ int tdg_plan_destroy(tdg_plan_t *pl)
     pl->d_prim_cnt.release();
     pl->d_cand_cnt.release();
     pl->d_grad_tune.release();
+    pl->d_tune_tasks.release();
+    pl->d_tune_mol.release();
     pl->d_btasks.release();
     pl->d_bmol.release();
     pl->d_bargs.release();
@@ -1534,7 +1549,12 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             if ((rc = lead->d_bargs.alloc(n))) return rc;
             HIP_TRY(hipMemcpyAsync(lead->d_bargs.p, margs.data(), sizeof(DerivArgs) * n, hipMemcpyHostToDevice, st));
             a.batch = lead->d_bargs.p;
-            a.lds_atoms = 0; // gradients of many molecules: direct FP64 atomics
+            // team kernels keep the gradient of one molecule at a time in LDS (sized for the
+            // largest molecule); the wavefront kernels add to the global gradients directly
+            int max_atoms = 0;
+            for (int m = 0; m < n; ++m) max_atoms = std::max(max_atoms, pls[m]->n_atoms);
+            a.n_atoms = max_atoms;
+            a.lds_atoms = (3 * max_atoms * 8 <= 24 * 1024) ? 1 : 0;
         }
         auto set_span = [&](DerivArgs &x, long long b, long long e) {
             x.tasks = tasks + b;
@@ -1546,7 +1566,8 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             need_tune |= !tuned[c] && ch.seg_end[c][1] > ch.seg_begin[c][0];
         if (lead->prm.autotune && lead->prm.kernel_variant < 0 && need_tune) {
             // autotuner: time the kernel variants of each class on this call's task list
-            // (into scratch gradients) and keep the fastest for later calls.  The wavefront
+            // (a strided sample of at most kTuneTasks tasks for a large class; into scratch
+            // gradients) and keep the fastest for later calls.  The wavefront
             // design is a candidate for classes with >= 27 components, the two team designs
             // for every class.  With the mixed route
             // it also decides the precision per class: the FP32-routed quartets run in FP32
@@ -1568,8 +1589,11 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                 if ((rc = lead->d_grad_tune.alloc((size_t)3 * lead->n_atoms))) return rc;
                 at.grad = lead->d_grad_tune.p;
             }
-            // fastest variant of precision pr over tasks [b, e): (ms, variant)
-            // fastest variant of precision pr over the task ranges [b0, e0) and [b1, e1) (the
+            // task list the timing launches read: the call's own, or a strided sample of a
+            // large class (kTuneTasks at most)
+            const int2 *tt = tasks;
+            const int *tm = task_mol;
+            // fastest variant of precision pr over the task ranges [b0, e0) and [b1, e1) of tt (the
             // segments need not be adjacent: the learned veto compacts each in place)
             auto best_of = [&](int c, int pr, long long b0, long long e0, long long b1, long long e1, float &best,
                                int &bv) -> int {
@@ -1591,7 +1615,9 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                         for (int k = 0; k < (merge ? 1 : 2); ++k) {
                             const long long b = k ? b1 : b0, e = merge ? e1 : (k ? e1 : e0);
                             if (e <= b) continue;
-                            set_span(at, b, e);
+                            at.tasks = tt + b;
+                            at.task_mol = tm ? tm + b : nullptr;
+                            at.ntasks = e - b;
                             HIP_TRY(kLaunch[c](v, pr, at, lr, st, grid_max));
                         }
                         HIP_TRY(hipEventRecord(lead->ev_cls[1], st));
@@ -1604,10 +1630,32 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                 return TDG_OK;
             };
             for (int c = 0; c < kNumClasses; ++c) {
-                const long long b0 = ch.seg_begin[c][0], e0 = ch.seg_end[c][0];
-                const long long b1 = ch.seg_begin[c][1], e1 = ch.seg_end[c][1];
+                long long b0 = ch.seg_begin[c][0], e0 = ch.seg_end[c][0];
+                long long b1 = ch.seg_begin[c][1], e1 = ch.seg_end[c][1];
                 if (tuned[c] || (e0 <= b0 && e1 <= b1)) continue;
                 tuned[c] = true;
+                tt = tasks;
+                tm = task_mol;
+                const long long n0 = std::max(0LL, e0 - b0), n1 = std::max(0LL, e1 - b1);
+                const long long stride = (n0 + n1 + kTuneTasks - 1) / kTuneTasks;
+                if (stride > 1) {
+                    // every stride-th task of each range, the two samples adjacent
+                    const long long m0 = (n0 + stride - 1) / stride, m1 = (n1 + stride - 1) / stride;
+                    if ((rc = lead->d_tune_tasks.alloc(m0 + m1)) ||
+                        (task_mol && (rc = lead->d_tune_mol.alloc(m0 + m1))))
+                        return rc;
+                    int *dm = task_mol ? lead->d_tune_mol.p : nullptr;
+                    if (m0)
+                        hipLaunchKernelGGL(k_sample_tasks, dim3((unsigned)((m0 + 255) / 256)), dim3(256), 0, st, tasks,
+                                           task_mol, b0, stride, m0, lead->d_tune_tasks.p, dm);
+                    if (m1)
+                        hipLaunchKernelGGL(k_sample_tasks, dim3((unsigned)((m1 + 255) / 256)), dim3(256), 0, st, tasks,
+                                           task_mol, b1, stride, m1, lead->d_tune_tasks.p + m0, dm ? dm + m0 : nullptr);
+                    HIP_TRY(hipGetLastError());
+                    tt = lead->d_tune_tasks.p;
+                    tm = dm;
+                    b0 = 0; e0 = m0; b1 = m0; e1 = m0 + m1;
+                }
                 float t_all = 0.f, t64 = 0.f, t32 = 0.f;
                 int v_all = 0, v64 = 0, v32 = 0;
                 if ((rc = best_of(c, 0, b0, e0, b1, e1, t_all, v_all))) return rc;
