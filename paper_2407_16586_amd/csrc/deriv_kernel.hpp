@@ -374,8 +374,14 @@ k_deriv(const DerivArgs a)
         if constexpr (BATCH) {
             const int m0 = a.task_mol[base];
             if (a.lds_atoms && m0 != cur) { // block-uniform
+                // LDS operations of different wavefronts are not ordered by the barrier
+                // alone: every wavefront's pending LDS additions (issued without return at
+                // the end of the previous task) must land before the array is read, and
+                // the zeros before the next task adds to it
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
                 __syncthreads();
                 if (cur >= 0) flush_mol(cur);
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
                 __syncthreads();
                 cur = m0;
             }

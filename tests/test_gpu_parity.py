@@ -327,6 +327,32 @@ def test_batch_repeated_and_device(tdg, oracle_lib):
         assert np.abs(o.cpu().numpy() - oracle_lib.grad(m, tau=1e-10)).max() <= TOL
 
 
+@pytest.mark.parametrize("variant", [0, 2, 4])
+def test_batch_many_tasks_per_block_matches_single(tdg, variant):
+    """Droplets large enough that every block of a batched launch walks across molecules:
+    the per-molecule LDS gradient a block keeps and flushes must give the single-call
+    result, on repeated calls (a flush that reads the array before every wavefront's
+    additions have landed loses or misplaces contributions nondeterministically)."""
+    import torch
+    from paper_2407_16586_amd import synth
+    mols = synth.config2()[:6]
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    dens = [(t(m.P0), t(m.PD), t(m.R)) for m in mols]
+    outs = [torch.zeros((m.n_atoms, 3), dtype=torch.float64, device=dev) for m in mols]
+    plans = [tdg.Plan(m, schwarz_tol=1e-10, autotune=False, kernel_variant=variant) for m in mols]
+    for p, d, o in zip(plans, dens, outs):
+        p.grad_device(*d, o)
+    torch.cuda.synchronize()
+    single = [o.cpu().numpy().copy() for o in outs]
+    for rep in range(2):
+        tdg.grad_batch_device(plans, dens, outs)
+        torch.cuda.synchronize()
+        err = max(float(np.abs(o.cpu().numpy() - g).max()) for o, g in zip(outs, single))
+        _say("batched droplets variant", variant, "call", rep, "max |batch - single|", err)
+        assert err <= 1e-11
+
+
 def test_batch_argument_errors(tdg, mol0):
     p = tdg.Plan(mol0)
     with pytest.raises(tdg.TdgError):
