@@ -399,7 +399,9 @@ template <int MODE>
 __global__ void __launch_bounds__(256) k_screen(ScreenArgs s, const ScreenTable t)
 {
     constexpr int MAXCH = 96; // chunks whose masks a wavefront keeps in LDS (MODE 2)
+    constexpr int MAXG = 32;  // ket contraction groups whose prefix ends it keeps (MODE 2)
     __shared__ unsigned long long s_mask[MODE == 2 ? 4 : 1][MODE == 2 ? MAXCH : 1][2];
+    __shared__ int s_gend[MODE == 2 ? 4 : 1][MODE == 2 ? MAXG : 1];
     const int gw = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave));
     const int lane = threadIdx.x % kWave;
     const int wv = (threadIdx.x / kWave) & 3;
@@ -428,27 +430,37 @@ __global__ void __launch_bounds__(256) k_screen(ScreenArgs s, const ScreenTable 
     const int Ki = s.pair_K[i];
     const bool hot_i = s.mixed && s.pair_pmax[i] >= s.p64;
     const double famp_i = s.mixed ? s.pair_famp[i] : 0.0;
-    // survivor flags of ket j for this bra
-    auto test = [&](int j, bool &keep, bool &to32) {
-        keep = false;
-        to32 = false;
+    // survivor flags of ket j for this bra (j must be a valid index; valid = false gives
+    // no survivor).  Branch-free, so that the loads of several calls can be in flight
+    // together.
+    auto test = [&](int j, bool valid, bool &keep, bool &to32) {
         const int c = s.pair_sa[j], d = s.pair_sb[j];
         const bool one_center = (s.shell_atom[c] == ata) && (s.shell_atom[d] == ata) && (atb == ata);
-        if (one_center) return;
         const double bnd = Qi * s.pair_Q[j] * block_bound(bm_ab, s.bmax, s.n_shells, a, b, c, d);
-        keep = s.tau <= 0.0 || bnd >= s.tau;
+        keep = valid && !one_center && (s.tau <= 0.0 || bnd >= s.tau);
         to32 = keep && s.mixed && !hot_i && bnd * famp_i * s.pair_famp[j] < s.tau64 && s.pair_pmax[j] < s.p64;
     };
-    // end of the Q-sorted prefix of group g that can pass the bound
+    // end of the Q-sorted prefix of group g that can pass the bound: the first ket with
+    // Q < cut (Q sorted descending), found by the wavefront together -- each step probes
+    // 64 evenly spaced kets and keeps the interval between the last one at or above the
+    // cut and the first one below, so a group of n kets takes about log64(n) + 1
+    // dependent loads instead of log2(n)
     auto group_end = [&](int g) {
         const int g0 = s.grp_start[g], g1 = s.grp_start[g + 1];
         int hi = g1;
-        if (cut > 0.0) { // first ket in the group with Q < cut (Q sorted descending)
-            int lo = g0;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (s.pair_Q[mid] >= cut) lo = mid + 1; else hi = mid;
+        if (cut > 0.0) {
+            int lo = g0; // invariant: Q >= cut below lo, Q < cut from hi on
+            while (hi - lo > kWave) {
+                const long long span = hi - lo;
+                const int p = lo + (int)(span * lane / kWave);
+                const int t = __popcll(__ballot(s.pair_Q[p] >= cut));
+                const int nlo = t > 0 ? lo + (int)(span * (t - 1) / kWave) + 1 : lo;
+                const int nhi = t < kWave ? lo + (int)(span * t / kWave) : hi;
+                lo = nlo;
+                hi = nhi;
             }
+            const int p = lo + lane;
+            hi = lo + __popcll(__ballot(p < hi && s.pair_Q[p] >= cut));
         }
         if (s.pb == s.pk && hi > i + 1) hi = i + 1; // canonical: ket index <= bra index
         return hi;
@@ -457,30 +469,40 @@ __global__ void __launch_bounds__(256) k_screen(ScreenArgs s, const ScreenTable 
     long long out = MODE == 1 ? s.item_off[wid] : 0, out32 = (MODE == 1 && s.mixed) ? s.item_off32[wid] : 0;
     int cnt = 0, cnt32 = 0, k = 0;
     unsigned long long prim = 0, cand = 0;
+    constexpr int UNR = 4; // chunks of 64 kets tested together
     for (int g = s.grp0; g < s.grp1; ++g) {
         const int g0 = s.grp_start[g], hi = group_end(g);
+        if (MODE == 2 && g - s.grp0 < MAXG && lane == 0) s_gend[wv][g - s.grp0] = hi;
         if (hi > g0) cand += hi - g0;
-        for (int j0 = g0; j0 < hi; j0 += kWave, ++k) {
-            const int j = j0 + lane;
-            bool keep = false, to32 = false;
-            if (j < hi) {
-                test(j, keep, to32);
+        for (int jb = g0; jb < hi; jb += UNR * kWave) {
+            bool kp[UNR], t3[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int j = jb + u * kWave + lane;
+                test(j < hi ? j : hi - 1, j < hi, kp[u], t3[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u, ++k) {
+                const int j0 = jb + u * kWave;
+                if (j0 >= hi) break; // wavefront-uniform
+                const int j = j0 + lane;
+                const bool keep = kp[u], to32 = t3[u];
                 if (keep) prim += (unsigned long long)Ki * s.pair_K[j];
+                const unsigned long long m64 = __ballot(keep && !to32), m32 = __ballot(to32);
+                if (MODE == 1 && keep) {
+                    const long long pos = to32 ? out32 + __popcll(m32 & below) : out + __popcll(m64 & below);
+                    s.tasks[pos] = make_int2(i, j);
+                    if (s.task_mol) s.task_mol[pos] = s.mol;
+                }
+                if (MODE == 2 && k < MAXCH && lane == 0) {
+                    s_mask[wv][k][0] = m64;
+                    s_mask[wv][k][1] = m32;
+                }
+                out += __popcll(m64);
+                out32 += __popcll(m32);
+                cnt += __popcll(m64);
+                cnt32 += __popcll(m32);
             }
-            const unsigned long long m64 = __ballot(keep && !to32), m32 = __ballot(to32);
-            if (MODE == 1 && keep) {
-                const long long pos = to32 ? out32 + __popcll(m32 & below) : out + __popcll(m64 & below);
-                s.tasks[pos] = make_int2(i, j);
-                if (s.task_mol) s.task_mol[pos] = s.mol;
-            }
-            if (MODE == 2 && k < MAXCH && lane == 0) {
-                s_mask[wv][k][0] = m64;
-                s_mask[wv][k][1] = m32;
-            }
-            out += __popcll(m64);
-            out32 += __popcll(m32);
-            cnt += __popcll(m64);
-            cnt32 += __popcll(m32);
         }
     }
     if (MODE != 1) {
@@ -511,7 +533,7 @@ __global__ void __launch_bounds__(256) k_screen(ScreenArgs s, const ScreenTable 
         long long o64 = (long long)b64, o32 = (long long)b32;
         k = 0;
         for (int g = s.grp0; g < s.grp1; ++g) {
-            const int g0 = s.grp_start[g], hi = group_end(g);
+            const int g0 = s.grp_start[g], hi = g - s.grp0 < MAXG ? s_gend[wv][g - s.grp0] : group_end(g);
             for (int j0 = g0; j0 < hi; j0 += kWave, ++k) {
                 const int j = j0 + lane;
                 unsigned long long m64, m32;
@@ -519,8 +541,8 @@ __global__ void __launch_bounds__(256) k_screen(ScreenArgs s, const ScreenTable 
                     m64 = s_mask[wv][k][0];
                     m32 = s_mask[wv][k][1];
                 } else {
-                    bool keep = false, to32 = false;
-                    if (j < hi) test(j, keep, to32);
+                    bool keep, to32;
+                    test(j < hi ? j : hi - 1, j < hi, keep, to32);
                     m64 = __ballot(keep && !to32);
                     m32 = __ballot(to32);
                 }
