@@ -86,6 +86,32 @@ template <> __device__ __forceinline__ const double *rys_hw<3>() { return rys_he
 template <> __device__ __forceinline__ const double *rys_hw<4>() { return rys_herm_w_4; }
 template <> __device__ __forceinline__ const double *rys_hw<5>() { return rys_herm_w_5; }
 
+// Polynomial sum_k c[k] x^k of NC coefficients by Estrin's scheme: coefficient pairs
+// first, then pairs of pairs with x^2, x^4, ...  The dependency depth is about log2(NC)
+// instead of NC - 1 for Horner's rule, for the same number of multiply-adds plus the
+// powers of x; with |x| <= 1 (the table's intervals are centred) it is as accurate.
+template <int NC>
+__device__ __forceinline__ double poly_estrin(const double *c, double x)
+{
+    double v[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) v[k] = c[k];
+    double xp = x;
+    int n = NC;
+#pragma unroll
+    for (int level = 0; level < 8; ++level) {
+        if (n <= 1) break;
+#pragma unroll
+        for (int j = 0; j < (NC + 1) / 2; ++j) {
+            if (2 * j + 1 < n) v[j] = fma(v[2 * j + 1], xp, v[2 * j]);
+            else if (2 * j < n) v[j] = v[2 * j];
+        }
+        n = (n + 1) / 2;
+        xp = xp * xp;
+    }
+    return v[0];
+}
+
 // Root r (0-based, ascending) and weight of the N-point Rys rule at argument T >= 0:
 // sum_r w_r u_r^k = F_k(T) for k < 2N.
 template <int N>
@@ -96,14 +122,8 @@ __device__ __forceinline__ void rys_root(double T, int r, double &u, double &w)
         const double x = T - RYS_WIDTH * (j + 0.5);
         const double *cu = rys_poly<N>() + ((j * 2 * N) + r) * RYS_NCOEF;
         const double *cw = cu + N * RYS_NCOEF;
-        double a = cu[RYS_NCOEF - 1], b = cw[RYS_NCOEF - 1];
-#pragma unroll
-        for (int k = RYS_NCOEF - 2; k >= 0; --k) {
-            a = fma(a, x, cu[k]);
-            b = fma(b, x, cw[k]);
-        }
-        u = a;
-        w = b;
+        u = poly_estrin<RYS_NCOEF>(cu, x);
+        w = poly_estrin<RYS_NCOEF>(cw, x);
     } else {
         const double st = rsq64(T);
         const double xh = rys_hx<N>()[r] * st;
@@ -131,14 +151,8 @@ __device__ __forceinline__ void rys_root_lds(const double *tab, double T, int r,
         const double x = T - RYS_WIDTH * (j + 0.5);
         const double *cu = tab + ((j * 2 * N) + r) * RYS_NCOEF;
         const double *cw = cu + N * RYS_NCOEF;
-        double a = cu[RYS_NCOEF - 1], b = cw[RYS_NCOEF - 1];
-#pragma unroll
-        for (int k = RYS_NCOEF - 2; k >= 0; --k) {
-            a = fma(a, x, cu[k]);
-            b = fma(b, x, cw[k]);
-        }
-        u = a;
-        w = b;
+        u = poly_estrin<RYS_NCOEF>(cu, x);
+        w = poly_estrin<RYS_NCOEF>(cw, x);
     } else {
         const double st = rsq64(T);
         const double xh = rys_hx<N>()[r] * st;
