@@ -259,6 +259,8 @@ struct DerivClass {
     // short (few components, one root per lane); elsewhere the extra live registers
     // would cost occupancy
     static constexpr bool EARLY_PREFETCH = !ALLR && N <= 9;
+    // per-range lanes evaluate their roots interleaved where the per-root state is small
+    static constexpr int ROOT_UNROLL = (ALLR && N <= 9) ? RPL : 1;
 };
 
 // Shell-blocked densities: the record of the ordered shell pair (x, y) starts at
@@ -466,7 +468,7 @@ k_deriv(const DerivArgs a)
                         eta = seta * seta;
                         Tr *= eta;
                     }
-#pragma unroll 1
+#pragma unroll K::ROOT_UNROLL
                     for (int rr = 0; rr < RPL; ++rr) {
                     const int ir = RPL == 1 ? ir0 : rr;
                     double u, w;
