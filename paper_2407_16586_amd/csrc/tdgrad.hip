@@ -579,7 +579,7 @@ __global__ void k_zero(double *p, long long n)
 // fused screening: copy the used part of every region to its place in the packed list;
 // one block per piece of a region, moves[3 r] = (source, destination, count)
 constexpr long long kPackPiece = 4096; // tasks per piece
-constexpr long long kTuneTasks = 1LL << 19; // tasks per class the autotuner times at most
+constexpr long long kTuneTasks = 1LL << 21; // tasks per class the autotuner times at most
 
 __global__ void k_pack_regions(const int2 *src, int2 *dst, const long long *moves)
 {
