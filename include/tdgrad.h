@@ -96,7 +96,8 @@ typedef struct {
     int32_t terms;      /* bit 1: Coulomb-type (J) terms, bit 2: full-range exchange (alpha),
                            bit 4: long-range exchange (beta); 7 = all */
     int32_t autotune;   /* 1: on the plan's first tdg_grad_jk call, time the kernel variants
-                           of each angular class on that call's tasks and keep the fastest;
+                           of each angular class on that call's tasks (every k-th task of a
+                           class holding more than 2^21) and keep the fastest;
                            in mixed mode also run a class's FP32-routed quartets in FP64 (one
                            launch for the class) when that measures faster than the split */
     int32_t kernel_variant; /* -1: per-class default or autotuned choice; 0: team-per-quartet
