@@ -11,8 +11,6 @@ struct DerivArgs {
     const int *shell_atom;  // [n_shells]
     const int *shell_ao;    // [n_shells]
     const int *pair_sa, *pair_sb, *pair_ppoff, *pair_npp; // sorted shell pairs
-    const double *pp_p, *pp_Px, *pp_Py, *pp_Pz, *pp_c, *pp_za, *pp_zb; // primitive pairs
-    const double *pp_ip;    // 1/p of each primitive pair
     const double2 *pp_rec;  // per primitive pair, 4 x double2: (p, 1/p) (c, za) (zb, Px) (Py, Pz)
     const double *dens;     // shell-blocked P, D, R records with the angular normalisation folded in
     int n_bf;

@@ -131,7 +131,7 @@ struct tdg_plan {
     DevBuf<int> d_shell_atom, d_shell_ao, d_shell_l;
     DevBuf<int> d_pair_sa, d_pair_sb, d_pair_ppoff, d_pair_npp, d_pair_K;
     DevBuf<double> d_pair_Q;
-    DevBuf<double> d_pp_p, d_pp_Px, d_pp_Py, d_pp_Pz, d_pp_c, d_pp_za, d_pp_zb, d_pp_ip;
+    DevBuf<double> d_pp_p, d_pp_Px, d_pp_Py, d_pp_Pz, d_pp_c; // per-field copy for the Schwarz kernel
     DevBuf<double> d_pp_rec; // the same eight values per primitive pair as one 64-byte record
     DevBuf<double> d_ang;                  // angular normalisation per AO
     DevBuf<int> d_grp_start;
@@ -847,7 +847,7 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
         (rc = pl->d_pair_sa.upload(sa)) || (rc = pl->d_pair_sb.upload(sb)) || (rc = pl->d_pair_ppoff.upload(off)) ||
         (rc = pl->d_pair_npp.upload(cnt)) || (rc = pl->d_pp_p.upload(pp[0])) || (rc = pl->d_pp_Px.upload(pp[1])) ||
         (rc = pl->d_pp_Py.upload(pp[2])) || (rc = pl->d_pp_Pz.upload(pp[3])) || (rc = pl->d_pp_c.upload(pp[4])) ||
-        (rc = pl->d_pp_za.upload(pp[5])) || (rc = pl->d_pp_zb.upload(pp[6])) || (rc = pl->d_ang.upload(ang)))
+        (rc = pl->d_ang.upload(ang)))
         return rc;
 
     // Schwarz per pair class: pairs grouped by class for the templated kernel
@@ -862,8 +862,7 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
         build_pp(pr, off, cnt, pp);
         if ((rc = pl->d_pair_sa.upload(sa)) || (rc = pl->d_pair_sb.upload(sb)) || (rc = pl->d_pair_ppoff.upload(off)) ||
             (rc = pl->d_pair_npp.upload(cnt)) || (rc = pl->d_pp_p.upload(pp[0])) || (rc = pl->d_pp_Px.upload(pp[1])) ||
-            (rc = pl->d_pp_Py.upload(pp[2])) || (rc = pl->d_pp_Pz.upload(pp[3])) || (rc = pl->d_pp_c.upload(pp[4])) ||
-            (rc = pl->d_pp_za.upload(pp[5])) || (rc = pl->d_pp_zb.upload(pp[6])))
+            (rc = pl->d_pp_Py.upload(pp[2])) || (rc = pl->d_pp_Pz.upload(pp[3])) || (rc = pl->d_pp_c.upload(pp[4])))
             return rc;
     }
     int cs[7] = {0};
@@ -963,8 +962,7 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
         (rc = pl->d_pair_ppoff.upload(off)) || (rc = pl->d_pair_npp.upload(cnt)) || (rc = pl->d_pair_K.upload(pl->pair_K)) ||
         (rc = pl->d_pair_Q.upload(pl->pair_Q)) || (rc = pl->d_grp_start.upload(pl->grp_start)) ||
         (rc = pl->d_pp_p.upload(pp[0])) || (rc = pl->d_pp_Px.upload(pp[1])) || (rc = pl->d_pp_Py.upload(pp[2])) ||
-        (rc = pl->d_pp_Pz.upload(pp[3])) || (rc = pl->d_pp_c.upload(pp[4])) || (rc = pl->d_pp_za.upload(pp[5])) ||
-        (rc = pl->d_pp_zb.upload(pp[6])) || (rc = pl->d_pp_ip.upload(pp[7])))
+        (rc = pl->d_pp_Pz.upload(pp[3])) || (rc = pl->d_pp_c.upload(pp[4])))
         return rc;
     {
         // record layout read by the team kernels: p, 1/p, c, za, zb, Px, Py, Pz
@@ -1075,7 +1073,7 @@ int tdg_plan_destroy(tdg_plan_t *pl)
     if (!pl) return TDG_OK;
     hipSetDevice(pl->device);
     DevBuf<double> *dbl[] = {&pl->d_coords, &pl->d_pair_Q, &pl->d_pp_p, &pl->d_pp_Px, &pl->d_pp_Py, &pl->d_pp_Pz,
-                             &pl->d_pp_c, &pl->d_pp_za, &pl->d_pp_zb, &pl->d_pp_ip, &pl->d_pp_rec, &pl->d_ang, &pl->d_in,
+                             &pl->d_pp_c, &pl->d_pp_rec, &pl->d_ang, &pl->d_in,
                              &pl->d_dens, &pl->d_grad};
     pl->d_bmax.release();
     for (auto *x : dbl) x->release();
@@ -1310,8 +1308,6 @@ static DerivArgs deriv_args(tdg_plan *pl)
     a.coords = pl->d_coords.p; a.shell_atom = pl->d_shell_atom.p; a.shell_ao = pl->d_shell_ao.p;
     a.pair_sa = pl->d_pair_sa.p; a.pair_sb = pl->d_pair_sb.p; a.pair_ppoff = pl->d_pair_ppoff.p;
     a.pair_npp = pl->d_pair_npp.p;
-    a.pp_p = pl->d_pp_p.p; a.pp_Px = pl->d_pp_Px.p; a.pp_Py = pl->d_pp_Py.p; a.pp_Pz = pl->d_pp_Pz.p;
-    a.pp_c = pl->d_pp_c.p; a.pp_za = pl->d_pp_za.p; a.pp_zb = pl->d_pp_zb.p; a.pp_ip = pl->d_pp_ip.p;
     a.pp_rec = reinterpret_cast<const double2 *>(pl->d_pp_rec.p);
     a.dens = pl->d_dens.p; a.n_bf = pl->n_bf;
     a.omega = pl->prm.omega; a.alpha = pl->prm.alpha; a.beta = pl->prm.beta; a.terms = pl->prm.terms;
