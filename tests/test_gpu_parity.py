@@ -353,6 +353,30 @@ def test_batch_many_tasks_per_block_matches_single(tdg, variant):
         assert err <= 1e-11
 
 
+def test_autotune_on_sampled_classes_matches_fixed_variants(tdg):
+    """An 89-atom droplet whose large classes hold more than 2^21 screened quartets: the
+    autotuner times those on every k-th task, and the tuned plan's gradient equals the
+    untuned plan's (FP64, same quartets) on its first and later calls."""
+    import torch
+    from paper_2407_16586_amd import synth
+    m = synth.config2()[1]
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    dens = (t(m.P0), t(m.PD), t(m.R))
+    out = torch.zeros((m.n_atoms, 3), dtype=torch.float64, device=dev)
+    ref_plan = tdg.Plan(m, schwarz_tol=1e-10, autotune=False)
+    st_ref = ref_plan.grad_device(*dens, out, stats=True)
+    ref = out.cpu().numpy().copy()
+    assert max(st_ref["class_quartets"]) > (1 << 21)
+    tuned = tdg.Plan(m, schwarz_tol=1e-10)
+    for call in range(2):
+        st = tuned.grad_device(*dens, out, stats=True)
+        err = float(np.abs(out.cpu().numpy() - ref).max())
+        _say("sampled autotuning, call", call, "max |tuned - untuned|", err, "variants", st["class_variant"])
+        assert st["quartets"] == st_ref["quartets"]
+        assert err <= 1e-11
+
+
 def test_batch_argument_errors(tdg, mol0):
     p = tdg.Plan(mol0)
     with pytest.raises(tdg.TdgError):
