@@ -134,8 +134,8 @@ def main():
                          "size that calibrates the HBM counters of a profiling run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md and not run here", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the quartet tasks would be "
+              "shared out over GPUs with one gradient all-reduce, which is not built here", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
