@@ -149,7 +149,7 @@ struct tdg_plan {
     std::vector<int> item_class_off;       // [22] offset of each class's items
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ev_cls[kNumClasses + 1] = {};
-    int variant[2][kNumClasses];           // kernel variant per (precision, class): 0 team, 1 wavefront, 2 direct team
+    int variant[2][kNumClasses];           // kernel variant per (precision, class), numbered as kernel_variant
     bool tf_ok[2][2][kNumClasses];         // transfer-form variants (0, 3) offered: no p/d on B or D and
                                            // the kernel keeps its tables in registers; else 2 (4) runs
     int split[kNumClasses];                // 1: the FP32-routed quartets of the class run in FP32; 0: the
@@ -757,7 +757,16 @@ static int class_ncomp(int c)
 
 // default variant before measurement: the wave-per-quartet kernel for classes whose
 // per-lane register tables would not fit (N >= 81 Cartesian components)
-static int default_variant(int c) { return class_ncomp(c) >= 81 ? 1 : 0; }
+// variant of a class when nothing is tuned (the autotuner's usual choice on the chain and
+// droplet workloads): per-range layouts for the smallest classes, the collapsed team
+// kernel in between, one wavefront per quartet for (dd|dd)
+static int default_variant(int c)
+{
+    const int n = class_ncomp(c);
+    if (n <= 3) return 3;
+    if (n <= 9) return 4;
+    return n >= 1296 ? 1 : 2;
+}
 static constexpr int kNumVariants = 5;
 
 template <int LA, int LB>
@@ -1862,7 +1871,8 @@ int tdg_collect(tdg_plan_t *pl, const double *P0, const double *PD, const double
         a.tasks = pl->d_tasks.p + seg_begin[c];
         a.ntasks = n;
         a.task_out = contrib.p + 12 * seg_begin[c];
-        HIP_TRY(kLaunch[c](default_variant(c), 0, a, lr, st, ncu * kGridPerCU));
+        // the plan's FP64 variant of the class (allowed forms only; tuned if a call tuned it)
+        HIP_TRY(kLaunch[c](pl->variant[0][c], 0, a, lr, st, ncu * kGridPerCU));
     }
     const long long ns = (total + stride - 1) / stride;
     const long long nout = std::min<long long>(ns, cap);
