@@ -250,7 +250,9 @@ struct DerivClass {
     static constexpr int LDS_G_BYTES = 40 * 1024 - (TAB_LDS ? TAB_N * 8 : 0);
     static constexpr int GB = (int)sizeof(F);
     static constexpr int TPB_LDS = LDS_G_BYTES / (GSTRIDE * GB) > 0 ? LDS_G_BYTES / (GSTRIDE * GB) : 1;
-    static constexpr int TPB = TPW * 4 < TPB_LDS ? TPW * 4 : TPB_LDS;
+    // two wavefronts per block (measured on the 60-atom chain: 1, 2, 4 wavefronts give
+    // 12.2, 10.8, 11.4 ms of mixed-path class kernels)
+    static constexpr int TPB = TPW * 2 < TPB_LDS ? TPW * 2 : TPB_LDS;
     static constexpr int WAVES = (TPB + TPW - 1) / TPW;
     static constexpr int BLOCK = WAVES * kWave;
     // ket primitive records loaded one primitive ahead: pays where a primitive's work is
