@@ -34,7 +34,11 @@
  *   - The caller owns every input and output buffer; the library never frees them.
  *   - A plan owns its device tables and work buffers; free it with tdg_plan_destroy.
  *   - ptr_kind = 1: densities and grad are device pointers on the plan's device;
- *     the call is asynchronous on hip_stream (the caller synchronises).
+ *     all work is queued on hip_stream and the gradient is written there, so the caller
+ *     synchronises the stream before reading it.  The call itself is not fully
+ *     asynchronous: it waits once on the stream (after screening) to read the task
+ *     counts that size the class launches, and again when stats are requested, so it
+ *     cannot be captured into a HIP graph.
  *     ptr_kind = 0: host pointers; the call returns after the result is copied.
  *   - Calls on one plan must not overlap (a plan holds one set of work buffers).
  */
@@ -118,6 +122,17 @@ typedef struct {
     double mixed_p64;   /* mixed mode: pairs with a primitive exponent sum >= this stay FP64
                            (INFINITY: no exponent cap) */
     int64_t max_tasks;  /* screened quartets held at once (chunking of large systems); 0 = 2^31 */
+    int32_t screening;  /* 0: density-multiplied Schwarz bound only (section II.E); an attached
+                           estimator is ignored.  1: the same bound, then the learned veto of the
+                           estimator attached with tdg_plan_set_screen_model (a call without one
+                           attached fails with TDG_ESTATE) */
+    int32_t deterministic; /* 1: bitwise repeatable gradients: tasks in a fixed order (no fused
+                              screening), per-class default kernel variants (no autotuning; an
+                              explicit kernel_variant still applies), each quartet's twelve values
+                              reduced over its lanes in a fixed order and summed per atom in task
+                              order (fixed blocks of tasks, then the blocks in order) instead of by
+                              floating-point atomics.  Slower; single-molecule calls of a batch run
+                              one after another.  0: atomics (default) */
 } tdg_params_t;
 
 /* Per-call statistics (optional output). */
@@ -140,24 +155,30 @@ typedef struct {
     double ms_kernels;         /* summed derivative-kernel time (HIP events), all chunks */
 } tdg_stats_t;
 
-/* Build a plan for one geometry and basis on HIP device `device`:
+/* Build a plan for one geometry and basis on HIP device `device` (section II.C: the
+ * contracted Cartesian functions of eq cartG and the presorted shell-pair lists of the
+ * paper's design; section II.E: the Schwarz factors of the screening bound):
  * normalisation, shell-pair tables, Schwarz factors Q_ab = sqrt(max (mu nu|mu nu)),
- * pair lists sorted by class, contraction degree and Q.
+ * pair lists sorted by class, contraction degree and Q.  The plan copies the basis.
  * Errors: TDG_EINVAL (bad pointers/indices), TDG_EUNSUPPORTED (l > 2 or
  * nprim > TDG_MAX_NPRIM), TDG_ENOMEM, TDG_EDEVICE. */
 int tdg_plan_create(const tdg_basis_t *basis, const tdg_params_t *params, int device,
                     tdg_plan_t **out);
 
-/* Two-electron gradient for one set of densities (eq dE_ao terms 4-5).
+/* Two-electron gradient for one set of densities (section II.A, eq dE_ao terms 4-5 with
+ * the densities of eq gamma; derivatives per section II.C eqs deri, deriv, ti,
+ * eriupdate; screening per section II.E).
  * P0, PDelta, R: [n_bf][n_bf] FP64 row-major; grad: [n_atoms][3] FP64,
- * overwritten.  ptr_kind 0: host pointers (synchronous); 1: device pointers,
- * asynchronous on hip_stream (a hipStream_t, NULL = default stream).
- * stats may be NULL; when given, the call synchronises the stream to fill it.
+ * overwritten.  ptr_kind 0: host pointers (synchronous); 1: device pointers on
+ * hip_stream (a hipStream_t, NULL = default stream; see Ownership for the one wait
+ * on the stream inside the call).  stats may be NULL; when given, the call
+ * synchronises the stream to fill it.
  * Errors: TDG_EINVAL, TDG_ENOMEM, TDG_EDEVICE, TDG_ESTATE. */
 int tdg_grad_jk(tdg_plan_t *plan, const double *P0, const double *PDelta, const double *R,
                 int32_t ptr_kind, void *hip_stream, double *grad, tdg_stats_t *stats);
 
-/* Gradients of n molecules in one pass: per molecule density preparation and
+/* Gradients of n molecules in one pass (the computation of tdg_grad_jk for each):
+ * per molecule density preparation and
  * screening, then one launch per angular class and precision over all the
  * molecules' quartets (a persistent grid striding over the concatenated task
  * lists).  plans[m] with densities P0[m], PDelta[m], R[m] writes grad[m]
@@ -208,6 +229,40 @@ int tdg_plan_set_screen_model(tdg_plan_t *plan, const tdg_mlp_t *model, double l
 int tdg_collect(tdg_plan_t *plan, const double *P0, const double *PDelta, const double *R,
                 int32_t ptr_kind, void *hip_stream, float *feat, float *target, int64_t cap,
                 int64_t stride, int64_t *n_out);
+
+/* Move the plan to a new geometry (same basis, shells on the same atoms): coords
+ * [n_atoms][3] bohr, host.  Rebuilds every geometry-dependent table (primitive-pair
+ * centres and factors, Schwarz factors and the sorted pair lists, section II.C/II.E) and
+ * keeps the kernel variants chosen by the autotuner, the learned region capacities of
+ * the fused screening and an attached estimator.  For finite-difference checks and
+ * geometry steps.  Errors: TDG_EINVAL (null pointers, non-finite coordinates),
+ * TDG_ENOMEM, TDG_EDEVICE; on error the plan is unchanged. */
+int tdg_plan_update_coords(tdg_plan_t *plan, const double *coords);
+
+/* Verification of the screening (section II.E): the shell quartets that pass the
+ * density-multiplied Schwarz bound for these densities, as the class kernels would
+ * receive them (learned veto not applied).  quartets: host [cap][4] int32, caller shell
+ * indices (a, b | c, d) of every stride-th surviving unique quartet (stride >= 1) in the
+ * library's canonical orientation (l_a >= l_b, l_c >= l_d, pair class of ab >= that of
+ * cd); order: class, then the precision list of the route (FP64, FP32; one list unless
+ * the plan is mixed), bra pair, ket pair.  *n_out = the number of survivors (of these
+ * at most cap are written).  Densities as in tdg_grad_jk.  Synchronous.
+ * Errors: TDG_EINVAL, TDG_ENOMEM, TDG_EDEVICE. */
+int tdg_screen_list(tdg_plan_t *plan, const double *P0, const double *PDelta, const double *R,
+                    int32_t ptr_kind, void *hip_stream, int32_t *quartets, int64_t cap, int64_t stride,
+                    int64_t *n_out);
+
+/* Verification of the class kernels one quartet at a time (eq dE_ao terms 4-5 restricted
+ * to one unique shell quartet, with its permutation degeneracy): for n shell quartets
+ * quartets [n][4] (host int32, caller shell indices in any order within and between
+ * the two pairs) writes out [n][4][3] (host FP64): the contributions to the gradient
+ * of the atoms of shells a, b, c, d as listed (hartree/bohr).  No screening.
+ * precision 0: FP64 kernels; 1: the FP32-table kernels of the mixed route.  Each
+ * quartet runs in the plan's kernel variant of its class.  Synchronous.
+ * Errors: TDG_EINVAL (bad indices), TDG_ENOMEM, TDG_EDEVICE. */
+int tdg_quartet_contribs(tdg_plan_t *plan, const double *P0, const double *PDelta, const double *R,
+                         int32_t ptr_kind, void *hip_stream, int64_t n, const int32_t *quartets,
+                         int32_t precision, double *out);
 
 /* Release a plan and its device memory (NULL is accepted). */
 int tdg_plan_destroy(tdg_plan_t *plan);

@@ -63,6 +63,8 @@ def lib():
         L.orc_energy.argtypes = [C.POINTER(Basis), vp, vp, vp, C.POINTER(Params), vp]
         L.orc_quartet_contribs.argtypes = [C.POINTER(Basis), vp, vp, vp, C.POINTER(Params), i64, vp, vp]
         L.orc_quartet_bounds.argtypes = [C.POINTER(Basis), vp, vp, vp, i64, vp, vp]
+        L.orc_screen_select.argtypes = [C.POINTER(Basis), vp, vp, vp, C.c_double, C.c_int, C.c_int, i64, vp,
+                                        vp, C.POINTER(i64)]
         L.orc_schwarz.argtypes = [C.POINTER(Basis), vp]
         L.orc_eri_tensor.argtypes = [C.POINTER(Basis), C.c_int, C.c_double, vp]
         L.orc_norm_coefs.argtypes = [C.POINTER(Basis), vp]
@@ -70,7 +72,7 @@ def lib():
         L.orc_prim_eri.restype = C.c_double
         L.orc_boys.argtypes = [C.c_int, C.c_double, vp]
         for f in ("orc_grad", "orc_grad_brute", "orc_energy", "orc_quartet_contribs",
-                  "orc_quartet_bounds", "orc_schwarz", "orc_eri_tensor", "orc_norm_coefs"):
+                  "orc_quartet_bounds", "orc_screen_select", "orc_schwarz", "orc_eri_tensor", "orc_norm_coefs"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -167,6 +169,24 @@ def quartet_bounds(mol, quartets):
     _check(lib().orc_quartet_bounds(C.byref(bb.b), _p(P0), _p(PD), _p(R), q.shape[0], _p(q),
                                     _p(out)), "quartet_bounds")
     return out
+
+
+def screen_select(mol, tau, keep=True, nthreads=0, cap=None, P0=None, PD=None, R=None):
+    """Unique shell quartets [n, 4] (a>=b, c>=d, pair ab >= pair cd; one-atom quartets left out)
+    whose screening bound is >= tau (keep) or < tau (not keep), and their bounds [n]."""
+    bb = _Bound(mol)
+    P0, PD, R = _dens(mol, P0, PD, R)
+    n = C.c_int64()
+    if cap is None:
+        _check(lib().orc_screen_select(C.byref(bb.b), _p(P0), _p(PD), _p(R), tau, int(keep), nthreads, 0,
+                                       None, None, C.byref(n)), "screen_select")
+        cap = n.value
+    q = np.zeros((max(cap, 1), 4), dtype=np.int32)
+    bnd = np.zeros(max(cap, 1))
+    _check(lib().orc_screen_select(C.byref(bb.b), _p(P0), _p(PD), _p(R), tau, int(keep), nthreads, cap,
+                                   _p(q), _p(bnd), C.byref(n)), "screen_select")
+    m = min(n.value, cap)
+    return q[:m], bnd[:m]
 
 
 def schwarz(mol):

@@ -860,6 +860,65 @@ int orc_quartet_bounds(const orc_basis_t *b, const double *P0, const double *PD,
     return 0;
 }
 
+/* The screening decision itself: every unique quartet (a>=b, c>=d, pair(ab)>=pair(cd), not
+ * all four shells on one atom) whose bound Q_ab Q_cd M_abcd is >= tau (keep = 1) or < tau
+ * (keep = 0), in that enumeration order; up to cap quartets [k][4] and their bounds are
+ * written, *n_out receives the full count. */
+int orc_screen_select(const orc_basis_t *b, const double *P0, const double *PD, const double *R, double tau,
+                      int keep, int nthreads, int64_t cap, int32_t *quartets, double *bound, int64_t *n_out)
+{
+    init_trip();
+    int rc = check_basis(b);
+    if (rc) return rc;
+    int nth = 1;
+#ifdef _OPENMP
+    nth = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    const int ns = b->n_shells;
+    oshell_t *sh = load_all(b);
+    dens_t d = {b->n_bf, P0, PD, R, 0.0, 0.0, 7};
+    screen_t scr;
+    screen_build(b, sh, &d, nth, &scr);
+    const int64_t npair = (int64_t)ns * (ns + 1) / 2;
+    int *pa = (int *)malloc(sizeof(int) * npair), *pb = (int *)malloc(sizeof(int) * npair);
+    for (int a = 0, k = 0; a < ns; ++a)
+        for (int c = 0; c <= a; ++c, ++k) { pa[k] = a; pb[k] = c; }
+    int64_t *cnt = (int64_t *)calloc(npair + 1, sizeof(int64_t));
+    for (int pass = 0; pass < 2; ++pass) {
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nth)
+        for (int64_t ab = 0; ab < npair; ++ab) {
+            const int a = pa[ab], bb = pb[ab];
+            const int at = b->shell_atom[a];
+            int64_t k = pass ? cnt[ab] : 0;
+            for (int64_t cd = 0; cd <= ab; ++cd) {
+                const int c = pa[cd], dd = pb[cd];
+                if (b->shell_atom[bb] == at && b->shell_atom[c] == at && b->shell_atom[dd] == at) continue;
+                const real q = quartet_bound(&scr, ns, a, bb, c, dd);
+                if ((q >= tau) != (keep != 0)) continue;
+                if (pass && k < cap) {
+                    quartets[4 * k] = a; quartets[4 * k + 1] = bb;
+                    quartets[4 * k + 2] = c; quartets[4 * k + 3] = dd;
+                    bound[k] = (double)q;
+                }
+                ++k;
+            }
+            if (!pass) cnt[ab] = k;
+        }
+        if (!pass) { /* exclusive prefix sums: first output slot of every bra pair */
+            int64_t acc = 0;
+            for (int64_t ab = 0; ab <= npair; ++ab) {
+                const int64_t v = ab < npair ? cnt[ab] : 0;
+                cnt[ab] = acc;
+                acc += v;
+            }
+        }
+    }
+    *n_out = cnt[npair];
+    free(cnt); free(pa); free(pb); free(sh);
+    screen_free(&scr);
+    return 0;
+}
+
 /* full AO integral tensor (normalised), tiny bases only: out[((mu*n+nu)*n+lam)*n+sig] */
 int orc_eri_tensor(const orc_basis_t *b, int op, double omega, double *out)
 {

@@ -627,19 +627,31 @@ k_deriv(const DerivArgs a)
                 }
             }
         }
-        if (valid) {
-            double out[12];
+        double out[12];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                out[3 + d] = acc[d];
-                out[6 + d] = acc[3 + d];
-                out[9 + d] = acc[6 + d];
-                out[d] = -(acc[d] + acc[3 + d] + acc[6 + d]); // translational invariance (eq ti)
+        for (int d = 0; d < 3; ++d) {
+            out[3 + d] = acc[d];
+            out[6 + d] = acc[3 + d];
+            out[9 + d] = acc[6 + d];
+            out[d] = -(acc[d] + acc[3 + d] + acc[6 + d]); // translational invariance (eq ti)
+        }
+        if (a.task_out) {
+            // per-quartet output: the team's lanes are summed in lane order (the same
+            // order on every run), and the first lane of the team stores the twelve values
+            const int lead = tw * TEAM;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                double v = __shfl(out[k], lead);
+#pragma unroll
+                for (int q = 1; q < TEAM; ++q) v += __shfl(out[k], lead + q);
+                out[k] = v;
             }
-            if (a.task_out) {
+            if (valid && r == 0) {
 #pragma unroll
-                for (int k = 0; k < 12; ++k) atomic_add_global(&a.task_out[12 * t + k], out[k]);
-            } else {
+                for (int k = 0; k < 12; ++k) a.task_out[12 * t + k] = out[k];
+            }
+        } else if (valid) {
+            {
                 const int at[4] = {atA, atB, atC, atD};
 #pragma unroll
                 for (int X = 0; X < 4; ++X)

@@ -189,6 +189,11 @@ struct tdg_plan {
     DevBuf<long long> d_fcap, d_freg, d_moves;
     DevBuf<int2> d_ftasks;
     int ncu = 0;                           // compute units of the plan's device
+    // copy of the caller's basis (tdg_plan_update_coords rebuilds the plan from it)
+    std::vector<double> b_coords, b_exps, b_coefs;
+    std::vector<int> b_nprim, b_primoff;
+    // deterministic reduction: per-task values and per-block partial gradients
+    DevBuf<double> d_tout, d_part;
     // host-side state of the current call
     std::vector<int> h_cnt, h_cnt32;
     std::vector<unsigned long long> h_prim, h_cand;
@@ -591,6 +596,56 @@ __global__ void k_pack_regions(const int2 *src, int2 *dst, const long long *move
     for (long long k = threadIdx.x; k < n; k += blockDim.x) dst[to + k] = src[from + k];
 }
 
+// ======================================================================= deterministic reduction
+// Per-atom sums of per-quartet values vals[t][12] (centres A, B, C, D of task t) in a
+// fixed order: block b sums the tasks [b per_block, (b+1) per_block) in task order into
+// partial[b][3 n_atoms], then k_det_final adds the blocks in block order.  Inside a
+// block (one wavefront) gradient entry g belongs to lane g % 64 alone, which adds its
+// values one task after another, so no two additions to an entry race and the result
+// does not depend on timing.
+constexpr int kDetBlocks = 1024;            // partial gradients per reduction at most
+constexpr long long kDetChunk = 1LL << 23;  // tasks per chunk in deterministic mode (768 MiB of values)
+
+__global__ void __launch_bounds__(64) k_det_reduce(const int2 *tasks, long long n, long long per_block,
+                                                   const double *vals, const int *pair_sa, const int *pair_sb,
+                                                   const int *shell_atom, int n_atoms, int use_lds, double *partial)
+{
+    extern __shared__ double s_acc[];
+    const int lane = threadIdx.x;
+    const int n3 = 3 * n_atoms;
+    double *acc = use_lds ? s_acc : partial + (size_t)blockIdx.x * n3;
+    for (int g = lane; g < n3; g += kWave) acc[g] = 0.0;
+    const long long t0 = (long long)blockIdx.x * per_block;
+    const long long t1 = t0 + per_block < n ? t0 + per_block : n;
+    for (long long t = t0; t < t1; ++t) {
+        const int2 tk = tasks[t];
+        const int at[4] = {shell_atom[pair_sa[tk.x]], shell_atom[pair_sb[tk.x]], shell_atom[pair_sa[tk.y]],
+                           shell_atom[pair_sb[tk.y]]};
+        const double *v = vals + 12 * t;
+#pragma unroll
+        for (int X = 0; X < 4; ++X)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int g = 3 * at[X] + d;
+                if (g % kWave == lane) acc[g] += v[3 * X + d];
+            }
+    }
+    if (use_lds)
+        for (int g = lane; g < n3; g += kWave) partial[(size_t)blockIdx.x * n3 + g] = acc[g];
+}
+
+// grad[g] += sum over blocks b of partial[b][g]: one wavefront per entry, lanes take the
+// blocks lane, lane + 64, ... in order, then a fixed butterfly over the lanes
+__global__ void __launch_bounds__(256) k_det_final(const double *partial, int nblk, int n3, double *grad)
+{
+    const int g = blockIdx.x * 4 + threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    if (g >= n3) return;
+    double v = 0.0;
+    for (int b = lane; b < nblk; b += kWave) v += partial[(size_t)b * n3 + g];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) grad[g] += v;
+}
+
 // ======================================================================= dispatch
 // ======================================================================= learned screening
 // Features of a shell quartet for the contribution estimator (10 used of 16):
@@ -789,6 +844,11 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
     pl->shell_atom.assign(b->shell_atom, b->shell_atom + ns);
     pl->shell_l.assign(b->shell_l, b->shell_l + ns);
     pl->shell_ao.assign(b->shell_ao_off, b->shell_ao_off + ns);
+    pl->b_coords.assign(b->coords, b->coords + 3 * b->n_atoms);
+    pl->b_exps.assign(b->exps, b->exps + b->n_prims);
+    pl->b_coefs.assign(b->coefs, b->coefs + b->n_prims);
+    pl->b_nprim.assign(b->shell_nprim, b->shell_nprim + ns);
+    pl->b_primoff.assign(b->shell_prim_off, b->shell_prim_off + ns);
     int nbf = 0;
     for (int s = 0; s < ns; ++s) nbf = std::max(nbf, b->shell_ao_off[s] + ncart(b->shell_l[s]));
     pl->n_bf = nbf;
@@ -1064,6 +1124,11 @@ int tdg_plan_create(const tdg_basis_t *basis, const tdg_params_t *params, int de
     if ((params->terms & 4) && !(params->omega > 0.0)) return fail(TDG_EINVAL, "long-range term needs omega > 0");
     if (params->kernel_variant < -1 || params->kernel_variant > 4)
         return fail(TDG_EINVAL, "kernel_variant must be -1 or 0..4");
+    if (params->screening != 0 && params->screening != 1)
+        return fail(TDG_EINVAL, "screening must be 0 (Schwarz bound) or 1 (bound + learned veto)");
+    if (params->deterministic != 0 && params->deterministic != 1)
+        return fail(TDG_EINVAL, "deterministic must be 0 or 1");
+    if (params->max_tasks < 0) return fail(TDG_EINVAL, "max_tasks must be >= 0");
     int ndev = 0;
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(TDG_EINVAL, "device %d not present (%d devices)", device, ndev);
@@ -1116,6 +1181,8 @@ int tdg_plan_destroy(tdg_plan_t *pl)
     pl->d_freg.release();
     pl->d_moves.release();
     pl->d_ftasks.release();
+    pl->d_tout.release();
+    pl->d_part.release();
     for (auto &e : pl->ev_cls)
         if (e) hipEventDestroy(e);
     pl->d_mx.release();
@@ -1448,6 +1515,11 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
     HIP_TRY(hipSetDevice(lead->device));
     int rc;
     const bool batched = n > 1;
+    // deterministic mode (single molecule): tasks in count-pass order, default variants,
+    // per-task values reduced in a fixed order (k_det_reduce, k_det_final)
+    const bool det = !batched && lead->prm.deterministic;
+    const bool use_ml = !batched && lead->prm.screening == 1;
+    if (use_ml && !lead->ml) return fail(TDG_ESTATE, "screening = 1 needs an estimator (tdg_plan_set_screen_model)");
     // screening: one fused launch when the previous call sized the regions, else (and
     // after an overflow) the count pass, per-item offsets on the host and the fill pass
     bool fused = false;
@@ -1455,7 +1527,7 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
     int2 *ftasks = nullptr;
     for (int m = 0; m < n; ++m)
         if ((rc = prep_density(pls[m], P0[m], PD[m], R[m], ptr_kind, st))) return rc;
-    if (!batched && lead->fused_ready) {
+    if (!batched && !det && lead->fused_ready) {
         bool ok = false;
         if ((rc = fused_screen(lead, st, fch, ftasks, ok))) return rc;
         fused = ok;
@@ -1472,7 +1544,8 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
     if (batched || fused) {
         chunks.push_back({0, 0});
     } else {
-        const long long cap = lead->prm.max_tasks > 0 ? lead->prm.max_tasks : (1LL << 31);
+        long long cap = lead->prm.max_tasks > 0 ? lead->prm.max_tasks : (1LL << 31);
+        if (det) cap = std::min(cap, kDetChunk);
         const int nitems = lead->item_class_off[kNumClasses];
         std::vector<char> act(kNumClasses);
         for (int c = 0; c < kNumClasses; ++c) act[c] = class_active(lead, c);
@@ -1567,13 +1640,14 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
         }
         HIP_TRY(hipGetLastError());
         } // two-pass task generation
-        if (!batched && lead->ml) {
+        if (use_ml) {
             long long sk = 0;
             if ((rc = ml_filter(lead, tasks, ch.seg_begin, ch.seg_end, st, sk))) return rc;
             ml_skipped += sk;
         }
         // class kernels
         DerivArgs a = deriv_args(lead);
+        if (det) a.lds_atoms = 0;
         if (batched) {
             std::vector<DerivArgs> margs(n);
             for (int m = 0; m < n; ++m) margs[m] = deriv_args(pls[m]);
@@ -1591,11 +1665,12 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             x.tasks = tasks + b;
             x.task_mol = task_mol ? task_mol + b : nullptr;
             x.ntasks = e - b;
+            x.task_out = det ? lead->d_tout.p + 12 * b : nullptr;
         };
         bool need_tune = false;
         for (int c = 0; c < kNumClasses; ++c)
             need_tune |= !tuned[c] && ch.seg_end[c][1] > ch.seg_begin[c][0];
-        if (lead->prm.autotune && lead->prm.kernel_variant < 0 && need_tune) {
+        if (lead->prm.autotune && lead->prm.kernel_variant < 0 && need_tune && !det) {
             // autotuner: time the kernel variants of each class on this call's task list
             // (a strided sample of at most kTuneTasks tasks for a large class; into scratch
             // gradients) and keep the fastest for later calls.  The wavefront
@@ -1706,6 +1781,13 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             HIP_TRY(hipStreamSynchronize(st));
             d_targs.release();
         }
+        if (det) {
+            // every class writes its quartets' twelve values; zeroed first (the wavefront
+            // kernels add their lanes' values)
+            const long long nv = 12 * std::max<long long>(ch.seg_end[kNumClasses - 1][1], 1);
+            if ((rc = lead->d_tout.alloc(nv))) return rc;
+            hipLaunchKernelGGL(k_zero, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, st, lead->d_tout.p, nv);
+        }
         HIP_TRY(hipEventRecord(lead->ev0, st));
         for (int c = 0; c < kNumClasses; ++c) {
             HIP_TRY(hipEventRecord(lead->ev_cls[c], st));
@@ -1727,6 +1809,27 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             }
         }
         HIP_TRY(hipEventRecord(lead->ev_cls[kNumClasses], st));
+        if (det) {
+            // per-atom sums in a fixed order, segment by segment (a learned veto leaves
+            // unused entries between the compacted segments)
+            const int n3 = 3 * lead->n_atoms;
+            const int use_lds = (size_t)n3 * sizeof(double) <= 64 * 1024 ? 1 : 0;
+            if ((rc = lead->d_part.alloc((size_t)kDetBlocks * n3))) return rc;
+            for (int c = 0; c < kNumClasses; ++c)
+                for (int pr = 0; pr < 2; ++pr) {
+                    const long long b = ch.seg_begin[c][pr], nt = ch.seg_end[c][pr] - b;
+                    if (nt <= 0) continue;
+                    const long long per = std::max<long long>(256, (nt + kDetBlocks - 1) / kDetBlocks);
+                    const int nblk = (int)((nt + per - 1) / per);
+                    hipLaunchKernelGGL(k_det_reduce, dim3(nblk), dim3(kWave), use_lds ? (size_t)n3 * sizeof(double) : 0,
+                                       st, tasks + b, nt, per, lead->d_tout.p + 12 * b, lead->d_pair_sa.p,
+                                       lead->d_pair_sb.p, lead->d_shell_atom.p, lead->n_atoms, use_lds,
+                                       lead->d_part.p);
+                    hipLaunchKernelGGL(k_det_final, dim3((unsigned)((n3 + 3) / 4)), dim3(256), 0, st, lead->d_part.p,
+                                       nblk, n3, lead->d_grad.p);
+                }
+            HIP_TRY(hipGetLastError());
+        }
         HIP_TRY(hipEventRecord(lead->ev1, st));
         for (int c = 0; c < kNumClasses; ++c) {
             const long long n64 = ch.seg_end[c][0] - ch.seg_begin[c][0], n32 = ch.seg_end[c][1] - ch.seg_begin[c][1];
@@ -1809,6 +1912,31 @@ int tdg_grad_jk_batch(int32_t n, tdg_plan_t *const *plans, const double *const *
             return fail(TDG_EINVAL, "plan %d differs from plan 0 in device or method parameters", m);
         for (int k = 0; k < m; ++k)
             if (plans[k] == plans[m]) return fail(TDG_EINVAL, "plan %d appears twice in the batch", m);
+        if (x.deterministic != y.deterministic)
+            return fail(TDG_EINVAL, "plan %d differs from plan 0 in the deterministic mode", m);
+    }
+    if (plans[0]->prm.deterministic) {
+        // one molecule after another (the fixed-order reduction is per molecule)
+        tdg_stats_t acc{}, one{};
+        for (int m = 0; m < n; ++m) {
+            const int rc = run_molecules(1, plans + m, P0 + m, PD + m, R + m, ptr_kind, (hipStream_t)hip_stream,
+                                         grad + m, stats ? &one : nullptr);
+            if (rc) return rc;
+            if (stats) {
+                acc.quartets += one.quartets; acc.prim_quartets += one.prim_quartets;
+                acc.candidates += one.candidates; acc.fp32_quartets += one.fp32_quartets;
+                acc.chunks += one.chunks; acc.ms_total += one.ms_total; acc.ms_kernels += one.ms_kernels;
+                for (int c = 0; c < kNumClasses; ++c) {
+                    acc.class_quartets[c] += one.class_quartets[c];
+                    acc.class_prim_quartets[c] += one.class_prim_quartets[c];
+                    acc.class_fp32_quartets[c] += one.class_fp32_quartets[c];
+                    acc.class_ms[c] += one.class_ms[c];
+                    acc.class_variant[c] = one.class_variant[c];
+                }
+            }
+        }
+        if (stats) *stats = acc;
+        return TDG_OK;
     }
     return run_molecules(n, plans, P0, PD, R, ptr_kind, (hipStream_t)hip_stream, grad, stats);
 }
@@ -1884,6 +2012,245 @@ int tdg_collect(tdg_plan_t *pl, const double *P0, const double *PD, const double
     contrib.release();
     *n_out = nout;
     return TDG_OK;
+}
+
+} // extern "C"
+
+// ----------------------------------------------------------------------------------
+// Verification entry points and geometry updates.
+
+// count and fill passes for all classes of one molecule into pl->d_tasks (no chunking):
+// per class the FP64-routed list, then the FP32-routed list (mixed plans)
+static int two_pass_tasks(tdg_plan *pl, hipStream_t st, Chunk &ch)
+{
+    int rc;
+    if ((rc = count_pass(pl, st))) return rc;
+    HIP_TRY(hipStreamSynchronize(st));
+    const int nitems = pl->item_class_off[kNumClasses];
+    std::vector<long long> offs(std::max(nitems, 1), 0), offs32(std::max(nitems, 1), 0);
+    long long total = 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+        const bool act = class_active(pl, c);
+        for (int pr = 0; pr < 2; ++pr) {
+            ch.seg_begin[c][pr] = total;
+            for (int k = pl->item_class_off[c]; k < pl->item_class_off[c + 1]; ++k) {
+                (pr ? offs32 : offs)[k] = total;
+                if (act) total += pr ? pl->h_cnt32[k] : pl->h_cnt[k];
+            }
+            ch.seg_end[c][pr] = total;
+        }
+    }
+    ch.total = total;
+    if ((rc = pl->d_tasks.alloc(std::max<long long>(total, 1)))) return rc;
+    if (nitems) {
+        HIP_TRY(hipMemcpyAsync(pl->d_item_off.p, offs.data(), 8 * nitems, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(pl->d_item_off32.p, offs32.data(), 8 * nitems, hipMemcpyHostToDevice, st));
+    }
+    ScreenArgs s = screen_args(pl);
+    s.tasks = pl->d_tasks.p;
+    ScreenTable t{};
+    for (int c = 0; c < kNumClasses; ++c)
+        if (class_active(pl, c)) screen_add(pl, t, c);
+    screen_launch<1>(s, t, st);
+    HIP_TRY(hipGetLastError());
+    // the offsets are read by the fill pass before the host vectors go out of scope
+    HIP_TRY(hipStreamSynchronize(st));
+    return TDG_OK;
+}
+
+extern "C" {
+
+int tdg_plan_update_coords(tdg_plan_t *pl, const double *coords)
+{
+    g_err.clear();
+    if (!pl || !coords) return fail(TDG_EINVAL, "null argument");
+    for (int k = 0; k < 3 * pl->n_atoms; ++k)
+        if (!std::isfinite(coords[k])) return fail(TDG_EINVAL, "coordinate %d is not finite", k);
+    HIP_TRY(hipSetDevice(pl->device));
+    tdg_basis_t b{};
+    b.n_atoms = pl->n_atoms;
+    b.coords = coords;
+    b.n_shells = pl->n_shells;
+    b.shell_atom = pl->shell_atom.data();
+    b.shell_l = pl->shell_l.data();
+    b.shell_nprim = pl->b_nprim.data();
+    b.shell_prim_off = pl->b_primoff.data();
+    b.shell_ao_off = pl->shell_ao.data();
+    b.n_prims = pl->n_prims;
+    b.exps = pl->b_exps.data();
+    b.coefs = pl->b_coefs.data();
+    tdg_plan *np = new (std::nothrow) tdg_plan();
+    if (!np) return fail(TDG_ENOMEM, "host allocation failed");
+    np->device = pl->device;
+    np->prm = pl->prm;
+    int rc = build_plan(np, &b);
+    if (rc) {
+        const std::string msg = g_err;
+        tdg_plan_destroy(np);
+        g_err = msg;
+        return rc;
+    }
+    // state that does not depend on the geometry: tuned variants, precision split,
+    // region capacities (the contraction groups are the same), estimator
+    std::memcpy(np->variant, pl->variant, sizeof np->variant);
+    std::memcpy(np->bvariant, pl->bvariant, sizeof np->bvariant);
+    std::memcpy(np->split, pl->split, sizeof np->split);
+    std::memcpy(np->bsplit, pl->bsplit, sizeof np->bsplit);
+    std::memcpy(np->tuned, pl->tuned, sizeof np->tuned);
+    std::memcpy(np->btuned, pl->btuned, sizeof np->btuned);
+    if (np->fgrp_off == pl->fgrp_off) {
+        np->fcap = pl->fcap;
+        np->fused_ready = pl->fused_ready;
+    }
+    np->ml = pl->ml;
+    np->ml_log10 = pl->ml_log10;
+    np->ml_tau_hi = pl->ml_tau_hi;
+    np->ncu = pl->ncu;
+    // the caller's handle keeps pointing at pl: move the new tables in, the old ones out
+    tdg_plan old = std::move(*pl);
+    *pl = std::move(*np);
+    *np = std::move(old);
+    tdg_plan_destroy(np);
+    return TDG_OK;
+}
+
+int tdg_screen_list(tdg_plan_t *pl, const double *P0, const double *PD, const double *R, int32_t ptr_kind,
+                    void *hip_stream, int32_t *quartets, int64_t cap, int64_t stride, int64_t *n_out)
+{
+    g_err.clear();
+    if (!pl || !P0 || !PD || !R || !n_out || cap < 0 || stride < 1 || (cap > 0 && !quartets))
+        return fail(TDG_EINVAL, "bad arguments");
+    if (ptr_kind != 0 && ptr_kind != 1) return fail(TDG_EINVAL, "ptr_kind must be 0 or 1");
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipSetDevice(pl->device));
+    int rc;
+    Chunk ch;
+    if ((rc = prep_density(pl, P0, PD, R, ptr_kind, st)) || (rc = two_pass_tasks(pl, st, ch))) return rc;
+    const long long nw = std::min<long long>((ch.total + stride - 1) / stride, cap);
+    if (nw > 0) {
+        // the sampled tasks, gathered on the device (every stride-th one)
+        DevBuf<int2> d_s;
+        if ((rc = d_s.alloc(nw))) return rc;
+        hipLaunchKernelGGL(k_sample_tasks, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, pl->d_tasks.p,
+                           nullptr, 0LL, (long long)stride, nw, d_s.p, nullptr);
+        std::vector<int2> h(nw);
+        const hipError_t e = hipMemcpyAsync(h.data(), d_s.p, sizeof(int2) * nw, hipMemcpyDeviceToHost, st);
+        const hipError_t e2 = e == hipSuccess ? hipStreamSynchronize(st) : e;
+        d_s.release();
+        if (e2 != hipSuccess) return fail(TDG_EDEVICE, "survivor copy failed: %s", hipGetErrorString(e2));
+        for (long long k = 0; k < nw; ++k) {
+            quartets[4 * k] = pl->pair_sa[h[k].x];
+            quartets[4 * k + 1] = pl->pair_sb[h[k].x];
+            quartets[4 * k + 2] = pl->pair_sa[h[k].y];
+            quartets[4 * k + 3] = pl->pair_sb[h[k].y];
+        }
+    }
+    *n_out = ch.total;
+    return TDG_OK;
+}
+
+int tdg_quartet_contribs(tdg_plan_t *pl, const double *P0, const double *PD, const double *R, int32_t ptr_kind,
+                         void *hip_stream, int64_t n, const int32_t *quartets, int32_t precision, double *out)
+{
+    g_err.clear();
+    if (!pl || !P0 || !PD || !R || n < 0 || (n > 0 && (!quartets || !out))) return fail(TDG_EINVAL, "bad arguments");
+    if (ptr_kind != 0 && ptr_kind != 1) return fail(TDG_EINVAL, "ptr_kind must be 0 or 1");
+    if (precision != 0 && precision != 1) return fail(TDG_EINVAL, "precision must be 0 or 1");
+    const int ns = pl->n_shells;
+    // canonical task of every quartet and the centre (A, B, C, D) behind each listed shell
+    std::vector<int2> task(n);
+    std::vector<int> cls(n), pos(4 * n);
+    for (long long k = 0; k < n; ++k) {
+        const int *q = quartets + 4 * k;
+        for (int x = 0; x < 4; ++x)
+            if (q[x] < 0 || q[x] >= ns) return fail(TDG_EINVAL, "quartet %lld: shell index out of range", k);
+        auto sorted_pair = [&](int x, int y) {
+            const long long u = x >= y ? (long long)x * (x + 1) / 2 + y : (long long)y * (y + 1) / 2 + x;
+            return pl->user_pair_to_sorted[u];
+        };
+        int p1 = sorted_pair(q[0], q[1]), p2 = sorted_pair(q[2], q[3]);
+        auto pcls = [&](int i) { return pair_class(pl->shell_l[pl->pair_sa[i]], pl->shell_l[pl->pair_sb[i]]); };
+        const bool swap_pairs = pcls(p1) < pcls(p2);
+        const int bra = swap_pairs ? p2 : p1, ket = swap_pairs ? p1 : p2;
+        task[k] = make_int2(bra, ket);
+        int pb = pcls(bra), pk = pcls(ket), c = 0;
+        for (int x = 0; x < kNumClasses; ++x) {
+            int b_, k_;
+            class_pk(x, b_, k_);
+            if (b_ == pb && k_ == pk) c = x;
+        }
+        cls[k] = c;
+        // listed position -> centre: the pair (q0, q1) is the bra unless swapped; within a
+        // pair the first centre is the pair's first shell (equal shells: in order)
+        for (int half = 0; half < 2; ++half) {
+            const int pi = half == 0 ? p1 : p2;
+            const bool is_bra = (half == 0) != swap_pairs;
+            const int base = is_bra ? 0 : 2;
+            const int s0 = q[2 * half], s1 = q[2 * half + 1];
+            const bool flip = s0 != s1 && pl->pair_sa[pi] != s0;
+            pos[4 * k + 2 * half] = base + (flip ? 1 : 0);
+            pos[4 * k + 2 * half + 1] = base + (flip ? 0 : 1);
+        }
+    }
+    if (n == 0) return TDG_OK;
+    // tasks grouped by class (stable), one launch per class
+    std::vector<long long> order(n);
+    std::iota(order.begin(), order.end(), 0LL);
+    std::stable_sort(order.begin(), order.end(), [&](long long x, long long y) { return cls[x] < cls[y]; });
+    std::vector<int2> sorted(n);
+    for (long long k = 0; k < n; ++k) sorted[k] = task[order[k]];
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipSetDevice(pl->device));
+    int rc;
+    if ((rc = prep_density(pl, P0, PD, R, ptr_kind, st))) return rc;
+    DevBuf<int2> d_t;
+    DevBuf<double> d_o;
+    if ((rc = d_t.alloc(n)) || (rc = d_o.alloc(12 * n))) {
+        d_t.release();
+        return rc;
+    }
+    int err = TDG_OK;
+    do {
+        if (hipMemcpyAsync(d_t.p, sorted.data(), sizeof(int2) * n, hipMemcpyHostToDevice, st) != hipSuccess) {
+            err = fail(TDG_EDEVICE, "task upload failed");
+            break;
+        }
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)((12 * n + 255) / 256)), dim3(256), 0, st, d_o.p, 12 * n);
+        const bool lr = (pl->prm.terms & 4) && pl->prm.beta != 0.0;
+        if (!pl->ncu) {
+            hipDeviceProp_t prop;
+            pl->ncu = hipGetDeviceProperties(&prop, pl->device) == hipSuccess ? prop.multiProcessorCount : 256;
+        }
+        DerivArgs a = deriv_args(pl);
+        a.lds_atoms = 0;
+        long long b = 0;
+        while (b < n && err == TDG_OK) {
+            const int c = cls[order[b]];
+            long long e = b;
+            while (e < n && cls[order[e]] == c) ++e;
+            a.tasks = d_t.p + b;
+            a.ntasks = e - b;
+            a.task_out = d_o.p + 12 * b;
+            if (kLaunch[c](pl->variant[precision][c], precision, a, lr, st, pl->ncu * kGridPerCU) != hipSuccess)
+                err = fail(TDG_EDEVICE, "class %d launch failed", c);
+            b = e;
+        }
+        if (err) break;
+        std::vector<double> h(12 * n);
+        if (hipMemcpyAsync(h.data(), d_o.p, sizeof(double) * 12 * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            err = fail(TDG_EDEVICE, "result copy failed");
+            break;
+        }
+        for (long long k = 0; k < n; ++k) {
+            const long long q = order[k];
+            for (int x = 0; x < 4; ++x)
+                for (int d = 0; d < 3; ++d) out[12 * q + 3 * x + d] = h[12 * k + 3 * pos[4 * q + x] + d];
+        }
+    } while (0);
+    d_t.release();
+    d_o.release();
+    return err;
 }
 
 } // extern "C"

@@ -73,7 +73,8 @@ def tune_threshold(mol, est, ref, tau=1e-10, tol=1e-6, tau_hi=1e-6, thresholds=N
     """Largest veto threshold (log10 of a contribution) whose gradient is within tol of ref;
     returns (threshold, error, stats) — threshold None when even the smallest fails."""
     thresholds = thresholds if thresholds is not None else [-9.0, -9.5, -10.0, -10.5, -11.0, -11.5, -12.0, -13.0]
-    p = tdgrad.Plan(mol, schwarz_tol=tau, precision=precision)
+    p = tdgrad.Plan(mol, schwarz_tol=tau, precision=precision, screening=1)
+    p.set_screen_model(est, -1e30, 0.0)  # keeps every quartet while the kernel variants are tuned
     gradient(p, mol)  # tune kernel variants first
     best = (None, None, None)
     for thr in sorted(thresholds, reverse=True):

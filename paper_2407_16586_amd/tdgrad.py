@@ -23,6 +23,7 @@ CLASSES = tuple(PAIR_CLASSES[b] + PAIR_CLASSES[k] for b in range(6) for k in ran
 
 EXPORTED = ("tdg_plan_create", "tdg_grad_jk", "tdg_grad_jk_batch", "tdg_plan_destroy", "tdg_plan_dims",
             "tdg_plan_schwarz", "tdg_rys_rule", "tdg_plan_set_screen_model", "tdg_collect",
+            "tdg_plan_update_coords", "tdg_screen_list", "tdg_quartet_contribs",
             "tdg_mlp_create", "tdg_mlp_destroy", "tdg_mlp_nweights", "tdg_mlp_set_weights",
             "tdg_mlp_get_weights", "tdg_mlp_forward", "tdg_mlp_grad", "tdg_mlp_train_step",
             "tdg_last_error")
@@ -46,7 +47,8 @@ class Params(C.Structure):
     _fields_ = [("omega", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
                 ("schwarz_tol", C.c_double), ("precision", C.c_int32), ("terms", C.c_int32),
                 ("autotune", C.c_int32), ("kernel_variant", C.c_int32),
-                ("mixed_tau64", C.c_double), ("mixed_p64", C.c_double), ("max_tasks", C.c_int64)]
+                ("mixed_tau64", C.c_double), ("mixed_p64", C.c_double), ("max_tasks", C.c_int64),
+                ("screening", C.c_int32), ("deterministic", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -96,6 +98,10 @@ def lib():
         L.tdg_plan_set_screen_model.argtypes = [vp, vp, C.c_double, C.c_double]
         L.tdg_collect.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, C.c_int64, C.c_int64,
                                   C.POINTER(C.c_int64)]
+        L.tdg_plan_update_coords.argtypes = [vp, vp]
+        L.tdg_screen_list.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, C.c_int64, C.c_int64,
+                                      C.POINTER(C.c_int64)]
+        L.tdg_quartet_contribs.argtypes = [vp, vp, vp, vp, C.c_int32, vp, C.c_int64, vp, C.c_int32, vp]
         L.tdg_mlp_create.argtypes = [C.c_int, C.c_uint64, C.POINTER(vp)]
         L.tdg_mlp_destroy.argtypes = [vp]
         L.tdg_mlp_nweights.argtypes = []
@@ -125,7 +131,7 @@ class Plan:
 
     def __init__(self, mol, omega=None, alpha=None, beta=None, schwarz_tol=1e-10, terms=TERMS_ALL,
                  precision=0, device=0, autotune=True, kernel_variant=-1, mixed_tau64=0.1,
-                 mixed_p64=float("inf"), max_tasks=0):
+                 mixed_p64=float("inf"), max_tasks=0, screening=0, deterministic=False):
         self._keep = [np.ascontiguousarray(mol.coords, dtype=np.float64)]
         for name in ("shell_atom", "shell_l", "shell_nprim", "shell_prim_off", "shell_ao_off"):
             self._keep.append(np.ascontiguousarray(getattr(mol, name), dtype=np.int32))
@@ -136,7 +142,8 @@ class Plan:
                   _ptr(k[4]), _ptr(k[5]), mol.n_prims, _ptr(k[6]), _ptr(k[7]))
         self.params = Params(mol.omega if omega is None else omega, mol.alpha if alpha is None else alpha,
                              mol.beta if beta is None else beta, schwarz_tol, precision, terms,
-                             1 if autotune else 0, kernel_variant, mixed_tau64, mixed_p64, max_tasks)
+                             1 if autotune else 0, kernel_variant, mixed_tau64, mixed_p64, max_tasks,
+                             screening, 1 if deterministic else 0)
         h = C.c_void_p()
         _check(lib().tdg_plan_create(C.byref(b), C.byref(self.params), device, C.byref(h)))
         self._h = h
@@ -174,8 +181,41 @@ class Plan:
                                  C.byref(st) if stats else None))
         return (out, st.as_dict()) if stats else out
 
+    def update_coords(self, coords):
+        """Move the plan to new coordinates [n_atoms, 3] (bohr); see tdg_plan_update_coords."""
+        c = np.ascontiguousarray(coords, dtype=np.float64)
+        if c.shape != (self.n_atoms, 3):
+            raise ValueError(f"coords must be ({self.n_atoms}, 3), got {c.shape}")
+        _check(lib().tdg_plan_update_coords(self._h, _ptr(c)))
+
+    def screen_list(self, P0, PD, R, cap=None, stride=1):
+        """Every stride-th surviving shell quartet [n, 4] (caller shell indices, library
+        orientation) and the total number of survivors."""
+        c = lambda x: np.ascontiguousarray(x, dtype=np.float64)
+        P0, PD, R = c(P0), c(PD), c(R)
+        n = C.c_int64()
+        if cap is None:
+            _check(lib().tdg_screen_list(self._h, _ptr(P0), _ptr(PD), _ptr(R), 0, None, None, 0, stride,
+                                         C.byref(n)))
+            cap = (n.value + stride - 1) // stride
+        out = np.zeros((max(cap, 1), 4), dtype=np.int32)
+        _check(lib().tdg_screen_list(self._h, _ptr(P0), _ptr(PD), _ptr(R), 0, None, _ptr(out), cap, stride,
+                                     C.byref(n)))
+        return out[:min((n.value + stride - 1) // stride, cap)], n.value
+
+    def quartet_contribs(self, P0, PD, R, quartets, precision=0):
+        """Contributions [n, 4, 3] of listed shell quartets [n, 4] to the atoms of the listed shells."""
+        c = lambda x: np.ascontiguousarray(x, dtype=np.float64)
+        P0, PD, R = c(P0), c(PD), c(R)
+        q = np.ascontiguousarray(quartets, dtype=np.int32).reshape(-1, 4)
+        out = np.zeros((q.shape[0], 4, 3))
+        _check(lib().tdg_quartet_contribs(self._h, _ptr(P0), _ptr(PD), _ptr(R), 0, None, q.shape[0],
+                                          _ptr(q), precision, _ptr(out)))
+        return out
+
     def set_screen_model(self, model, log10_threshold=-12.0, tau_hi=1e-6):
-        """Attach a trained Estimator (or None) as a veto after the Schwarz screening."""
+        """Attach a trained Estimator (or None); it vetoes quartets after the Schwarz
+        screening in plans created with screening=1."""
         self._model = model
         _check(lib().tdg_plan_set_screen_model(self._h, model._h if model is not None else None,
                                                log10_threshold, tau_hi))

@@ -44,8 +44,10 @@ def test_veto_with_compacted_segments(precision):
     est = tdgrad.Estimator(seed=5)
     res = {}
     for prec in (0, precision):
-        p = tdgrad.Plan(m, schwarz_tol=1e-10, precision=prec)
+        p = tdgrad.Plan(m, schwarz_tol=1e-10, precision=prec, screening=1)
+        p.set_screen_model(est, -1e30, 0.0)   # keeps every quartet
         g0, s0 = p.grad(m.P0, m.PD, m.R, stats=True)
+        assert s0["ml_skipped"] == 0
         p.set_screen_model(est, 100.0, 1e-3)  # veto everything the bound does not keep
         g, st = p.grad(m.P0, m.PD, m.R, stats=True)
         assert st["ml_skipped"] > 0 and st["quartets"] > 0

@@ -36,6 +36,57 @@ def test_forward_matches_reference(tdg):
         assert err <= 2e-3 * max(1.0, np.abs(ref).max())
 
 
+def _bf16_forward_bound(w, X):
+    """Worst-case |BF16 network - exact FP64 network| per sample: the kernels round the input,
+    W1, the first hidden layer and W2 to BF16 (unit roundoff u = 2^-9 each); the bound
+    propagates those relative errors through the layers with absolute values (ReLU is
+    1-Lipschitz), plus FP32 accumulation (64 terms, 2^-24 each) at every layer."""
+    W1, b1, W2, b2, w3, b3 = ref_mlp.unpack(w)
+    u, f = 2.0 ** -9, 64 * 2.0 ** -24
+    x = np.abs(np.asarray(X, dtype=np.float64))
+    a1 = x @ np.abs(W1).T                     # scale of the first products
+    h1 = np.maximum(x @ W1.T + b1, 0.0)
+    e1 = (2 * u + u * u + f) * a1 + f * np.abs(b1)
+    eh1 = e1 + u * (np.abs(h1) + e1)          # rounding of h1 to BF16
+    a2 = (np.abs(h1) + eh1) @ np.abs(W2).T
+    e2 = eh1 @ np.abs(W2).T * (1 + u) + (u + f) * a2 + f * np.abs(b2)
+    h2 = np.maximum(np.maximum(x @ W1.T + b1, 0.0) @ W2.T + b2, 0.0)
+    return e2 @ np.abs(w3) + f * (np.abs(h2) @ np.abs(w3) + abs(b3))
+
+
+def test_forward_matches_exact_network(tdg):
+    """The BF16 kernels against the exact FP64 network (no rounding anywhere), within the
+    error that BF16 rounding of the operands can cause, sample by sample."""
+    import torch
+    est = tdg.Estimator(seed=6)
+    w = est.weights()
+    for n in (64, 3000):
+        X, _ = _data(n, 100 + n)
+        out = est.forward(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+        exact = ref_mlp.forward(w, X, bf=False)[0]
+        bound = _bf16_forward_bound(w, X)
+        err = np.abs(out - exact)
+        print("exact network", n, "max err", err.max(), "max bound", bound.max(),
+              "worst err/bound", (err / bound).max(), flush=True)
+        assert np.all(err <= bound)
+
+
+def test_gradient_matches_exact_network(tdg):
+    """Loss gradient of the BF16 kernels against the exact FP64 network's: BF16 operands in
+    three chained products give relative errors of a few 2^-9 per element; the norm of the
+    difference stays within 3 * 3 * 2^-9 of the norm (2^-9 per rounded operand)."""
+    import torch
+    est = tdg.Estimator(seed=8)
+    w = est.weights()
+    X, Y = _data(2000, 9)
+    loss, g = est.grad(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda())
+    rloss, rg = ref_mlp.loss_and_grad(w, X, Y, bf=False)
+    rel = np.linalg.norm(g - rg) / np.linalg.norm(rg)
+    print("exact network: loss", loss, rloss, "grad rel", rel, flush=True)
+    assert abs(loss - rloss) <= 9 * 2.0 ** -9 * max(1.0, rloss)
+    assert rel <= 9 * 2.0 ** -9
+
+
 def test_gradient_matches_reference(tdg):
     import torch
     est = tdg.Estimator(seed=4)
@@ -69,10 +120,11 @@ def test_veto_limits_and_collection(tdg, oracle_lib, mol0):
     dev = torch.device("cuda:0")
     t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
     P0, PD, R = t(mol0.P0), t(mol0.PD), t(mol0.R)
-    p = tdg.Plan(mol0, schwarz_tol=1e-10)
+    p0 = tdg.Plan(mol0, schwarz_tol=1e-10)
     out = torch.zeros((mol0.n_atoms, 3), dtype=torch.float64, device=dev)
-    base = p.grad_device(P0, PD, R, out, stats=True)
+    base = p0.grad_device(P0, PD, R, out, stats=True)
     g0 = out.cpu().numpy().copy()
+    p = tdg.Plan(mol0, schwarz_tol=1e-10, screening=1)
     est = tdg.Estimator(seed=1)
     p.set_screen_model(est, log10_threshold=-1e30, tau_hi=np.inf)  # keeps everything
     st = p.grad_device(P0, PD, R, out, stats=True)
@@ -87,6 +139,7 @@ def test_veto_limits_and_collection(tdg, oracle_lib, mol0):
     assert st["ml_skipped"] == 0
     assert np.abs(out.cpu().numpy() - oracle_lib.grad(mol0, tau=1e-10)).max() <= 1e-8
     p.set_screen_model(None)
+    p = p0
     feat = torch.zeros((100000, 16), dtype=torch.float32, device=dev)
     tgt = torch.zeros(100000, dtype=torch.float32, device=dev)
     n = p.collect(P0, PD, R, feat, tgt)
