@@ -177,6 +177,22 @@ int tdg_plan_create(const tdg_basis_t *basis, const tdg_params_t *params, int de
 int tdg_grad_jk(tdg_plan_t *plan, const double *P0, const double *PDelta, const double *R,
                 int32_t ptr_kind, void *hip_stream, double *grad, tdg_stats_t *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): tdg_grad_jk with device pointers (P0, PDelta, R,
+ * grad on the plan's device, work queued on hip_stream) that calls no hipMalloc, hipFree or
+ * other allocating routine.  The screened task list of each chunk goes to a static device
+ * buffer of 8,388,608 tasks (64 MiB, one per GPU the library runs on, held until the process
+ * ends); a larger task list runs as several chunks.  The plan's current kernel variants are
+ * used (tuned by an earlier tdg_grad_jk call, else the per-class defaults): no autotuning and
+ * no fused screening here.  Calls on one GPU share its buffer, whatever the plan: calls that
+ * overlap on one GPU race (the caller serialises them).  Like tdg_grad_jk it waits once on
+ * the stream to read the task counts.
+ * Errors: TDG_EINVAL (null pointers); TDG_EUNSUPPORTED for a deterministic plan, a plan with
+ * screening = 1, or when the survivors of one bra pair in one class exceed the buffer;
+ * TDG_EDEVICE. */
+int tdg_grad_jk_noalloc(tdg_plan_t *plan, const double *P0, const double *PDelta, const double *R,
+                        void *hip_stream, double *grad, tdg_stats_t *stats);
+
 /* Gradients of n molecules in one pass (the computation of tdg_grad_jk for each):
  * per molecule density preparation and
  * screening, then one launch per angular class and precision over all the

@@ -19,6 +19,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -1507,10 +1508,15 @@ static void region_counts(tdg_plan *pl)
     }
 }
 
+// static_tasks (non-null): the allocation-free variant -- the task list of every chunk goes
+// to static_tasks (at most static_cap tasks), and nothing that allocates device memory runs
+// (no fused screening, no autotuning, no learned veto, no deterministic reduction)
 static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, const double *const *PD,
-                         const double *const *R, int ptr_kind, hipStream_t st, double *const *grad, tdg_stats_t *stats)
+                         const double *const *R, int ptr_kind, hipStream_t st, double *const *grad, tdg_stats_t *stats,
+                         int2 *static_tasks = nullptr, long long static_cap = 0)
 {
     const auto t_start = std::chrono::steady_clock::now();
+    const bool noalloc = static_tasks != nullptr;
     tdg_plan *lead = pls[0];
     HIP_TRY(hipSetDevice(lead->device));
     int rc;
@@ -1527,7 +1533,7 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
     int2 *ftasks = nullptr;
     for (int m = 0; m < n; ++m)
         if ((rc = prep_density(pls[m], P0[m], PD[m], R[m], ptr_kind, st))) return rc;
-    if (!batched && !det && lead->fused_ready) {
+    if (!batched && !det && !noalloc && lead->fused_ready) {
         bool ok = false;
         if ((rc = fused_screen(lead, st, fch, ftasks, ok))) return rc;
         fused = ok;
@@ -1546,6 +1552,7 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
     } else {
         long long cap = lead->prm.max_tasks > 0 ? lead->prm.max_tasks : (1LL << 31);
         if (det) cap = std::min(cap, kDetChunk);
+        if (noalloc) cap = std::min(cap, static_cap);
         const int nitems = lead->item_class_off[kNumClasses];
         std::vector<char> act(kNumClasses);
         for (int c = 0; c < kNumClasses; ++c) act[c] = class_active(lead, c);
@@ -1606,7 +1613,13 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                 }
                 ch.seg_end[c][pr] = total;
             }
-        if (batched) {
+        if (noalloc) {
+            if (total > static_cap)
+                return fail(TDG_EUNSUPPORTED,
+                            "%lld screened quartets of one bra pair exceed the static task buffer (%lld)", total,
+                            static_cap);
+            tasks = static_tasks;
+        } else if (batched) {
             if ((rc = lead->d_btasks.alloc(std::max<long long>(total, 1))) ||
                 (rc = lead->d_bmol.alloc(std::max<long long>(total, 1))))
                 return rc;
@@ -1670,7 +1683,7 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
         bool need_tune = false;
         for (int c = 0; c < kNumClasses; ++c)
             need_tune |= !tuned[c] && ch.seg_end[c][1] > ch.seg_begin[c][0];
-        if (lead->prm.autotune && lead->prm.kernel_variant < 0 && need_tune && !det) {
+        if (lead->prm.autotune && lead->prm.kernel_variant < 0 && need_tune && !det && !noalloc) {
             // autotuner: time the kernel variants of each class on this call's task list
             // (a strided sample of at most kTuneTasks tasks for a large class; into scratch
             // gradients) and keep the fastest for later calls.  The wavefront
@@ -1895,6 +1908,46 @@ int tdg_grad_jk(tdg_plan_t *pl, const double *P0, const double *PD, const double
     if (!P0 || !PD || !R || !grad) return fail(TDG_EINVAL, "null density or output pointer");
     if (ptr_kind != 0 && ptr_kind != 1) return fail(TDG_EINVAL, "ptr_kind must be 0 or 1");
     return run_molecules(1, &pl, &P0, &PD, &R, ptr_kind, (hipStream_t)hip_stream, &grad, stats);
+}
+
+} // extern "C"
+
+// Task list of the allocation-free entry point: one per GPU, in a file-scope device array
+// (its host-side name is not a device address: host code uses the address that
+// hipGetSymbolAddress returns for the current device).  Fully written by the fill pass of
+// every chunk before the class kernels read it, so nothing needs clearing between calls.
+constexpr long long kStaticTasks = 1LL << 23; // 8,388,608 tasks, 64 MiB
+static __device__ __align__(256) int2 scratch[kStaticTasks];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static int2 *g_scratch_ptr[kMaxDevices] = {};
+
+extern "C" {
+
+int tdg_grad_jk_noalloc(tdg_plan_t *pl, const double *P0, const double *PD, const double *R, void *hip_stream,
+                        double *grad, tdg_stats_t *stats)
+{
+    g_err.clear();
+    if (!pl) return fail(TDG_EINVAL, "null plan");
+    if (!P0 || !PD || !R || !grad) return fail(TDG_EINVAL, "null density or output pointer");
+    if (pl->prm.deterministic) return fail(TDG_EUNSUPPORTED, "the allocation-free call has no deterministic mode");
+    if (pl->prm.screening != 0) return fail(TDG_EUNSUPPORTED, "the allocation-free call has no learned veto");
+    if (pl->device < 0 || pl->device >= kMaxDevices) return fail(TDG_EUNSUPPORTED, "device index %d", pl->device);
+    HIP_TRY(hipSetDevice(pl->device));
+    int2 *tasks = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[pl->device]) {
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return fail(TDG_EDEVICE, "hipGetSymbolAddress of the static task buffer failed: %s",
+                            hipGetErrorString(e));
+            g_scratch_ptr[pl->device] = static_cast<int2 *>(p);
+        }
+        tasks = g_scratch_ptr[pl->device];
+    }
+    return run_molecules(1, &pl, &P0, &PD, &R, 1, (hipStream_t)hip_stream, &grad, stats, tasks, kStaticTasks);
 }
 
 int tdg_grad_jk_batch(int32_t n, tdg_plan_t *const *plans, const double *const *P0, const double *const *PD,

@@ -23,7 +23,7 @@ CLASSES = tuple(PAIR_CLASSES[b] + PAIR_CLASSES[k] for b in range(6) for k in ran
 
 EXPORTED = ("tdg_plan_create", "tdg_grad_jk", "tdg_grad_jk_batch", "tdg_plan_destroy", "tdg_plan_dims",
             "tdg_plan_schwarz", "tdg_rys_rule", "tdg_plan_set_screen_model", "tdg_collect",
-            "tdg_plan_update_coords", "tdg_screen_list", "tdg_quartet_contribs",
+            "tdg_plan_update_coords", "tdg_screen_list", "tdg_quartet_contribs", "tdg_grad_jk_noalloc",
             "tdg_mlp_create", "tdg_mlp_destroy", "tdg_mlp_nweights", "tdg_mlp_set_weights",
             "tdg_mlp_get_weights", "tdg_mlp_forward", "tdg_mlp_grad", "tdg_mlp_train_step",
             "tdg_last_error")
@@ -98,6 +98,7 @@ def lib():
         L.tdg_plan_set_screen_model.argtypes = [vp, vp, C.c_double, C.c_double]
         L.tdg_collect.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, C.c_int64, C.c_int64,
                                   C.POINTER(C.c_int64)]
+        L.tdg_grad_jk_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(Stats)]
         L.tdg_plan_update_coords.argtypes = [vp, vp]
         L.tdg_screen_list.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, C.c_int64, C.c_int64,
                                       C.POINTER(C.c_int64)]
@@ -245,6 +246,22 @@ class Plan:
         st = Stats()
         _check(lib().tdg_grad_jk(self._h, P0.data_ptr(), PD.data_ptr(), R.data_ptr(), 1, s,
                                  out.data_ptr(), C.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
+
+    def grad_device_noalloc(self, P0, PD, R, out, stream=None, stats=False):
+        """As grad_device, through tdg_grad_jk_noalloc (no device allocation in the call)."""
+        import torch
+        n = self.n_bf
+        for x in (P0, PD, R):
+            if x.dtype != torch.float64 or not x.is_contiguous() or tuple(x.shape) != (n, n) or not x.is_cuda:
+                raise ValueError("densities must be contiguous float64 device tensors of shape (n_bf, n_bf)")
+        if out.dtype != torch.float64 or not out.is_contiguous() or tuple(out.shape) != (self.n_atoms, 3):
+            raise ValueError("out must be a contiguous float64 device tensor (n_atoms, 3)")
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        st = Stats()
+        _check(lib().tdg_grad_jk_noalloc(self._h, P0.data_ptr(), PD.data_ptr(), R.data_ptr(), s,
+                                         out.data_ptr(), C.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
 
