@@ -120,7 +120,7 @@ typedef struct {
                            alone, which is fastest but leaves the error unbounded by the
                            router: it scales with the largest quartet contributions */
     double mixed_p64;   /* mixed mode: pairs with a primitive exponent sum >= this stay FP64
-                           (INFINITY: no exponent cap) */
+                           (INFINITY: no exponent cap; the Python binding's default is 1e4) */
     int64_t max_tasks;  /* screened quartets held at once (chunking of large systems); 0 = 2^31 */
     int32_t screening;  /* 0: density-multiplied Schwarz bound only (section II.E); an attached
                            estimator is ignored.  1: the same bound, then the learned veto of the
@@ -133,6 +133,10 @@ typedef struct {
                               order (fixed blocks of tasks, then the blocks in order) instead of by
                               floating-point atomics.  Slower; single-molecule calls of a batch run
                               one after another.  0: atomics (default) */
+    int32_t streams;    /* the class kernels of a call run side by side on this many HIP streams
+                           (the caller's stream and streams - 1 of the plan's, joined back into
+                           the caller's stream before the call's last step); 1 = all on the
+                           caller's stream, 0 = 4 (the maximum) */
 } tdg_params_t;
 
 /* Per-call statistics (optional output). */
@@ -194,13 +198,15 @@ int tdg_grad_jk_noalloc(tdg_plan_t *plan, const double *P0, const double *PDelta
                         void *hip_stream, double *grad, tdg_stats_t *stats);
 
 /* Gradients of n molecules in one pass (the computation of tdg_grad_jk for each):
- * per molecule density preparation and
- * screening, then one launch per angular class and precision over all the
- * molecules' quartets (a persistent grid striding over the concatenated task
- * lists).  plans[m] with densities P0[m], PDelta[m], R[m] writes grad[m]
- * ([n_atoms(m)][3]).  All plans must share device, omega, alpha, beta, terms and
- * precision, and appear once.  Work buffers of the batch belong to plans[0]; its
- * autotuned variants for batched calls are kept separately from single calls.
+ * per molecule density preparation and the screening count pass, one host
+ * synchronisation for all task counts, the fill passes into one task list, then one
+ * launch graph of the (molecule, class) kernel items, largest expected work first, spread
+ * over the lead plan's streams (see streams) so that the GPU runs small items beside large
+ * ones.  plans[m] with densities P0[m], PDelta[m], R[m] writes grad[m] ([n_atoms(m)][3]).
+ * All plans must share device, omega, alpha, beta, terms, precision and deterministic, and
+ * appear once.  Work buffers of the batch belong to plans[0]; its kernel variants for
+ * batched calls (autotuned on the molecule with the most quartets of each class) are kept
+ * separately from single calls.  Deterministic plans run one molecule after another.
  * Errors: as tdg_grad_jk. */
 int tdg_grad_jk_batch(int32_t n, tdg_plan_t *const *plans, const double *const *P0,
                       const double *const *PDelta, const double *const *R, int32_t ptr_kind,

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -149,7 +150,13 @@ struct tdg_plan {
     DevBuf<int2> d_tasks;
     std::vector<int> item_class_off;       // [22] offset of each class's items
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipEvent_t ev_cls[kNumClasses + 1] = {};
+    hipEvent_t ev_cls[kNumClasses + 1] = {};   // class start events (and the autotuner's timing)
+    std::vector<hipEvent_t> ev_item;           // start and end of every class-kernel item of a call
+    // class kernels spread over nstreams streams: the caller's and nstreams - 1 of the plan's
+    static constexpr int kMaxAux = 3;
+    int nstreams = 1;
+    hipStream_t aux[kMaxAux] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kMaxAux] = {};
     int variant[2][kNumClasses];           // kernel variant per (precision, class), numbered as kernel_variant
     bool tf_ok[2][2][kNumClasses];         // transfer-form variants (0, 3) offered: no p/d on B or D and
                                            // the kernel keeps its tables in registers; else 2 (4) runs
@@ -165,10 +172,7 @@ struct tdg_plan {
     DevBuf<double> d_grad_tune;            // scratch gradient for the tuning launches
     DevBuf<int2> d_tune_tasks;             // strided sample of a class's tasks for the autotuner
     DevBuf<int> d_tune_mol;
-    // buffers of batched calls led by this plan (the first plan of tdg_grad_jk_batch)
-    DevBuf<int2> d_btasks;
-    DevBuf<int> d_bmol;
-    DevBuf<DerivArgs> d_bargs;
+    // kernel variants of batched calls led by this plan (the first plan of tdg_grad_jk_batch)
     int bvariant[2][kNumClasses];
     int bsplit[kNumClasses];
     bool btuned[kNumClasses] = {};
@@ -369,8 +373,6 @@ struct ScreenArgs {
     int mixed;                    // 1: route to FP32 unless bound >= tau64 or an exponent sum >= p64
     double tau64, p64;
     int2 *tasks;
-    int *task_mol;                // batched fill: molecule index per task (null: one molecule)
-    int mol;
     unsigned long long *prim_cnt; // per class
     unsigned long long *cand_cnt; // per class
     // fused pass: per contraction group gb of the bra pair class, task counters, regions of the
@@ -408,7 +410,9 @@ __global__ void __launch_bounds__(256) k_screen(ScreenArgs s, const ScreenTable 
     constexpr int MAXG = 32;  // ket contraction groups whose prefix ends it keeps (MODE 2)
     __shared__ unsigned long long s_mask[MODE == 2 ? 4 : 1][MODE == 2 ? MAXCH : 1][2];
     __shared__ int s_gend[MODE == 2 ? 4 : 1][MODE == 2 ? MAXG : 1];
-    const int gw = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave));
+    // wavefront index in 64-bit arithmetic: a large system has more than 2^26 (class, bra) items
+    const int gw = __builtin_amdgcn_readfirstlane(
+        (int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave));
     const int lane = threadIdx.x % kWave;
     const int wv = (threadIdx.x / kWave) & 3;
     if (gw >= t.wave_start[t.n]) return;
@@ -498,7 +502,6 @@ __global__ void __launch_bounds__(256) k_screen(ScreenArgs s, const ScreenTable 
                 if (MODE == 1 && keep) {
                     const long long pos = to32 ? out32 + __popcll(m32 & below) : out + __popcll(m64 & below);
                     s.tasks[pos] = make_int2(i, j);
-                    if (s.task_mol) s.task_mol[pos] = s.mol;
                 }
                 if (MODE == 2 && k < MAXCH && lane == 0) {
                     s_mask[wv][k][0] = m64;
@@ -1049,7 +1052,16 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
         }
         if ((rc = pl->d_pp_rec.upload(rec))) return rc;
     }
-    // screening items: (class, bra pair)
+    // screening items: (class, bra pair), one wavefront each, indexed in int
+    {
+        long long items = 0;
+        for (int c = 0; c < kNumClasses; ++c) {
+            int pb, pk;
+            class_pk(c, pb, pk);
+            items += cs[pb + 1] - cs[pb];
+        }
+        if (items >= INT32_MAX) return fail(TDG_EUNSUPPORTED, "%lld screening items (class, bra pair) exceed 2^31", items);
+    }
     pl->item_class_off.assign(kNumClasses + 1, 0);
     for (int c = 0; c < kNumClasses; ++c) {
         int pb, pk;
@@ -1066,6 +1078,15 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
     HIP_TRY(hipEventCreate(&pl->ev0));
     HIP_TRY(hipEventCreate(&pl->ev1));
     for (auto &e : pl->ev_cls) HIP_TRY(hipEventCreate(&e));
+    pl->nstreams = pl->prm.streams > 0 ? std::min(pl->prm.streams, tdg_plan::kMaxAux + 1) : tdg_plan::kMaxAux + 1;
+    if (pl->nstreams > 1) {
+        HIP_TRY(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming));
+        for (int k = 0; k + 1 < pl->nstreams; ++k) {
+            // default priority (streams of other priorities are not used anywhere)
+            HIP_TRY(hipStreamCreateWithFlags(&pl->aux[k], hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&pl->ev_join[k], hipEventDisableTiming));
+        }
+    }
     const bool lr = (pl->prm.terms & 4) && pl->prm.beta != 0.0;
     for (int pr = 0; pr < 2; ++pr)
         for (int c = 0; c < kNumClasses; ++c) {
@@ -1130,6 +1151,7 @@ int tdg_plan_create(const tdg_basis_t *basis, const tdg_params_t *params, int de
     if (params->deterministic != 0 && params->deterministic != 1)
         return fail(TDG_EINVAL, "deterministic must be 0 or 1");
     if (params->max_tasks < 0) return fail(TDG_EINVAL, "max_tasks must be >= 0");
+    if (params->streams < 0) return fail(TDG_EINVAL, "streams must be >= 0");
     int ndev = 0;
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(TDG_EINVAL, "device %d not present (%d devices)", device, ndev);
@@ -1165,9 +1187,6 @@ int tdg_plan_destroy(tdg_plan_t *pl)
     pl->d_grad_tune.release();
     pl->d_tune_tasks.release();
     pl->d_tune_mol.release();
-    pl->d_btasks.release();
-    pl->d_bmol.release();
-    pl->d_bargs.release();
     pl->d_pair_pmax.release();
     pl->d_pair_famp.release();
     pl->d_pair_pmin.release();
@@ -1186,6 +1205,13 @@ int tdg_plan_destroy(tdg_plan_t *pl)
     pl->d_part.release();
     for (auto &e : pl->ev_cls)
         if (e) hipEventDestroy(e);
+    for (auto &e : pl->ev_item)
+        if (e) hipEventDestroy(e);
+    for (int k = 0; k < tdg_plan::kMaxAux; ++k) {
+        if (pl->aux[k]) hipStreamDestroy(pl->aux[k]);
+        if (pl->ev_join[k]) hipEventDestroy(pl->ev_join[k]);
+    }
+    if (pl->ev_fork) hipEventDestroy(pl->ev_fork);
     pl->d_mx.release();
     pl->d_tasks.release();
     if (pl->ev0) hipEventDestroy(pl->ev0);
@@ -1233,13 +1259,14 @@ static void screen_add(tdg_plan *pl, ScreenTable &t, int c, int skip = 0, int nb
     it.bgrp0 = pl->pc_grp_start[pb]; it.bgrp1 = pl->pc_grp_start[pb + 1];
     it.fgrp_base = pl->fgrp_off.empty() ? 0 : pl->fgrp_off[c];
     if (it.nbra <= 0) return;
-    t.wave_start[t.n + 1] = t.wave_start[t.n] + it.nbra;
+    t.wave_start[t.n + 1] = (int)std::min<long long>((long long)t.wave_start[t.n] + it.nbra, INT32_MAX);
     ++t.n;
 }
 
 template <int MODE>
 static void screen_launch(const ScreenArgs &s, const ScreenTable &t, hipStream_t st)
 {
+    // screen_add keeps wave_start below 2^31 (one wavefront per (class, bra pair) item)
     if (t.n) hipLaunchKernelGGL(k_screen<MODE>, dim3((t.wave_start[t.n] + 3) / 4), dim3(256), 0, st, s, t);
 }
 
@@ -1508,6 +1535,26 @@ static void region_counts(tdg_plan *pl)
     }
 }
 
+// timing events for n class-kernel items (created once, kept by the plan)
+static int ensure_item_events(tdg_plan *pl, int n)
+{
+    while ((int)pl->ev_item.size() < n) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        pl->ev_item.push_back(e);
+    }
+    return TDG_OK;
+}
+
+// screened quartets of class c (both lists) from the count pass
+static long long cls_count(const tdg_plan *pl, int c)
+{
+    long long n = 0;
+    for (int k = pl->item_class_off[c]; k < pl->item_class_off[c + 1]; ++k)
+        n += (long long)pl->h_cnt[k] + (pl->h_cnt32.empty() ? 0 : pl->h_cnt32[k]);
+    return n;
+}
+
 // static_tasks (non-null): the allocation-free variant -- the task list of every chunk goes
 // to static_tasks (at most static_cap tasks), and nothing that allocates device memory runs
 // (no fused screening, no autotuning, no learned veto, no deterministic reduction)
@@ -1583,137 +1630,119 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
     long long tot_quartets = 0, tot_fp32 = 0, ml_skipped = 0;
     long long cls_q[kNumClasses] = {0}, cls_q32[kNumClasses] = {0};
     double cls_ms[kNumClasses] = {0.0}, kern_ms = 0.0;
+    // class-kernel items: (molecule, class) with their FP64 and FP32 task ranges
+    struct Item {
+        int m, c;
+        long long b[2], e[2];
+        double cost;
+    };
+    std::vector<Item> items;
     for (size_t ci = 0; ci < chunks.size(); ++ci) {
         const int K0 = chunks[ci].first, K1 = chunks[ci].second;
         Chunk ch;
         int2 *tasks;
-        int *task_mol = nullptr;
+        // per molecule, the task ranges of each (class, list): [mb, me)
+        std::vector<std::array<std::array<long long, 2>, kNumClasses>> mb(n), me(n);
         if (fused) {
             ch = fch;
             tasks = ftasks;
-        } else {
-        std::vector<std::vector<long long>> offs(n), offs32(n);
-        for (int m = 0; m < n; ++m) {
-            offs[m].assign(pls[m]->item_class_off[kNumClasses], 0);
-            offs32[m].assign(pls[m]->item_class_off[kNumClasses], 0);
-        }
-        long long total = 0;
-        for (int c = 0; c < kNumClasses; ++c)
-            for (int pr = 0; pr < 2; ++pr) {
-                ch.seg_begin[c][pr] = total;
-                for (int m = 0; m < n; ++m) {
-                    tdg_plan *pl = pls[m];
-                    const bool act = class_active(pl, c);
-                    int lo = pl->item_class_off[c], hi = pl->item_class_off[c + 1];
-                    if (!batched) { lo = std::max(lo, K0); hi = std::min(hi, K1); }
-                    for (int k = lo; k < hi; ++k) {
-                        if (pr == 0) offs[m][k] = total; else offs32[m][k] = total;
-                        if (act) total += pr == 0 ? pl->h_cnt[k] : pl->h_cnt32[k];
-                    }
+            for (int c = 0; c < kNumClasses; ++c)
+                for (int pr = 0; pr < 2; ++pr) {
+                    mb[0][c][pr] = ch.seg_begin[c][pr];
+                    me[0][c][pr] = ch.seg_end[c][pr];
                 }
-                ch.seg_end[c][pr] = total;
-            }
-        if (noalloc) {
-            if (total > static_cap)
-                return fail(TDG_EUNSUPPORTED,
-                            "%lld screened quartets of one bra pair exceed the static task buffer (%lld)", total,
-                            static_cap);
-            tasks = static_tasks;
-        } else if (batched) {
-            if ((rc = lead->d_btasks.alloc(std::max<long long>(total, 1))) ||
-                (rc = lead->d_bmol.alloc(std::max<long long>(total, 1))))
-                return rc;
-            tasks = lead->d_btasks.p;
-            task_mol = lead->d_bmol.p;
         } else {
-            if ((rc = lead->d_tasks.alloc(std::max<long long>(total, 1)))) return rc;
-            tasks = lead->d_tasks.p;
-        }
-        for (int m = 0; m < n; ++m) {
-            tdg_plan *pl = pls[m];
-            const int i0 = batched ? 0 : K0, i1 = batched ? pl->item_class_off[kNumClasses] : K1;
-            if (i1 > i0) {
-                HIP_TRY(hipMemcpyAsync(pl->d_item_off.p + i0, offs[m].data() + i0, 8 * (i1 - i0), hipMemcpyHostToDevice, st));
-                if (pl->prm.precision == 1)
-                    HIP_TRY(hipMemcpyAsync(pl->d_item_off32.p + i0, offs32[m].data() + i0, 8 * (i1 - i0),
+            std::vector<std::vector<long long>> offs(n), offs32(n);
+            for (int m = 0; m < n; ++m) {
+                offs[m].assign(pls[m]->item_class_off[kNumClasses], 0);
+                offs32[m].assign(pls[m]->item_class_off[kNumClasses], 0);
+            }
+            long long total = 0;
+            for (int c = 0; c < kNumClasses; ++c)
+                for (int pr = 0; pr < 2; ++pr) {
+                    ch.seg_begin[c][pr] = total;
+                    for (int m = 0; m < n; ++m) {
+                        tdg_plan *pl = pls[m];
+                        const bool act = class_active(pl, c);
+                        int lo = pl->item_class_off[c], hi = pl->item_class_off[c + 1];
+                        if (!batched) { lo = std::max(lo, K0); hi = std::min(hi, K1); }
+                        mb[m][c][pr] = total;
+                        for (int k = lo; k < hi; ++k) {
+                            if (pr == 0) offs[m][k] = total; else offs32[m][k] = total;
+                            if (act) total += pr == 0 ? pl->h_cnt[k] : pl->h_cnt32[k];
+                        }
+                        me[m][c][pr] = total;
+                    }
+                    ch.seg_end[c][pr] = total;
+                }
+            ch.total = total;
+            if (noalloc) {
+                if (total > static_cap)
+                    return fail(TDG_EUNSUPPORTED,
+                                "%lld screened quartets of one bra pair exceed the static task buffer (%lld)", total,
+                                static_cap);
+                tasks = static_tasks;
+            } else {
+                if ((rc = lead->d_tasks.alloc(std::max<long long>(total, 1)))) return rc;
+                tasks = lead->d_tasks.p;
+            }
+            for (int m = 0; m < n; ++m) {
+                tdg_plan *pl = pls[m];
+                const int i0 = batched ? 0 : K0, i1 = batched ? pl->item_class_off[kNumClasses] : K1;
+                if (i1 > i0) {
+                    HIP_TRY(hipMemcpyAsync(pl->d_item_off.p + i0, offs[m].data() + i0, 8 * (i1 - i0),
                                            hipMemcpyHostToDevice, st));
+                    if (pl->prm.precision == 1)
+                        HIP_TRY(hipMemcpyAsync(pl->d_item_off32.p + i0, offs32[m].data() + i0, 8 * (i1 - i0),
+                                               hipMemcpyHostToDevice, st));
+                }
+                ScreenArgs s = screen_args(pl);
+                s.tasks = tasks;
+                ScreenTable t{};
+                for (int c = 0; c < kNumClasses; ++c) {
+                    if (!class_active(pl, c)) continue;
+                    const int lo = std::max(pl->item_class_off[c], i0), hi = std::min(pl->item_class_off[c + 1], i1);
+                    if (hi <= lo) continue;
+                    screen_add(pl, t, c, lo - pl->item_class_off[c], hi - lo);
+                }
+                screen_launch<1>(s, t, st);
             }
-            ScreenArgs s = screen_args(pl);
-            s.tasks = tasks;
-            s.task_mol = task_mol;
-            s.mol = m;
-            ScreenTable t{};
-            for (int c = 0; c < kNumClasses; ++c) {
-                if (!class_active(pl, c)) continue;
-                const int lo = std::max(pl->item_class_off[c], i0), hi = std::min(pl->item_class_off[c + 1], i1);
-                if (hi <= lo) continue;
-                screen_add(pl, t, c, lo - pl->item_class_off[c], hi - lo);
-            }
-            screen_launch<1>(s, t, st);
-        }
-        HIP_TRY(hipGetLastError());
+            HIP_TRY(hipGetLastError());
+            // the fill pass reads the offsets before the host vectors go out of scope
+            HIP_TRY(hipStreamSynchronize(st));
         } // two-pass task generation
         if (use_ml) {
             long long sk = 0;
             if ((rc = ml_filter(lead, tasks, ch.seg_begin, ch.seg_end, st, sk))) return rc;
             ml_skipped += sk;
+            for (int c = 0; c < kNumClasses; ++c)
+                for (int pr = 0; pr < 2; ++pr) {
+                    mb[0][c][pr] = ch.seg_begin[c][pr];
+                    me[0][c][pr] = ch.seg_end[c][pr];
+                }
         }
-        // class kernels
-        DerivArgs a = deriv_args(lead);
-        if (det) a.lds_atoms = 0;
-        if (batched) {
-            std::vector<DerivArgs> margs(n);
-            for (int m = 0; m < n; ++m) margs[m] = deriv_args(pls[m]);
-            if ((rc = lead->d_bargs.alloc(n))) return rc;
-            HIP_TRY(hipMemcpyAsync(lead->d_bargs.p, margs.data(), sizeof(DerivArgs) * n, hipMemcpyHostToDevice, st));
-            a.batch = lead->d_bargs.p;
-            // team kernels keep the gradient of one molecule at a time in LDS (sized for the
-            // largest molecule); the wavefront kernels add to the global gradients directly
-            int max_atoms = 0;
-            for (int m = 0; m < n; ++m) max_atoms = std::max(max_atoms, pls[m]->n_atoms);
-            a.n_atoms = max_atoms;
-            a.lds_atoms = (3 * max_atoms * 8 <= 24 * 1024) ? 1 : 0;
+        // per-molecule kernel arguments
+        std::vector<DerivArgs> margs(n);
+        for (int m = 0; m < n; ++m) {
+            margs[m] = deriv_args(pls[m]);
+            if (det) margs[m].lds_atoms = 0;
         }
-        auto set_span = [&](DerivArgs &x, long long b, long long e) {
-            x.tasks = tasks + b;
-            x.task_mol = task_mol ? task_mol + b : nullptr;
-            x.ntasks = e - b;
-            x.task_out = det ? lead->d_tout.p + 12 * b : nullptr;
-        };
         bool need_tune = false;
         for (int c = 0; c < kNumClasses; ++c)
             need_tune |= !tuned[c] && ch.seg_end[c][1] > ch.seg_begin[c][0];
         if (lead->prm.autotune && lead->prm.kernel_variant < 0 && need_tune && !det && !noalloc) {
-            // autotuner: time the kernel variants of each class on this call's task list
-            // (a strided sample of at most kTuneTasks tasks for a large class; into scratch
-            // gradients) and keep the fastest for later calls.  The wavefront
-            // design is a candidate for classes with >= 27 components, the two team designs
-            // for every class.  With the mixed route
-            // it also decides the precision per class: the FP32-routed quartets run in FP32
-            // only where FP64 over the whole class measures slower.
-            std::vector<DerivArgs> targs;
-            DerivArgs at = a;
-            DevBuf<DerivArgs> d_targs;
-            if (batched) {
-                targs.resize(n);
-                for (int m = 0; m < n; ++m) {
-                    targs[m] = deriv_args(pls[m]);
-                    if ((rc = pls[m]->d_grad_tune.alloc((size_t)3 * pls[m]->n_atoms))) return rc;
-                    targs[m].grad = pls[m]->d_grad_tune.p;
-                }
-                if ((rc = d_targs.alloc(n))) return rc;
-                HIP_TRY(hipMemcpyAsync(d_targs.p, targs.data(), sizeof(DerivArgs) * n, hipMemcpyHostToDevice, st));
-                at.batch = d_targs.p;
-            } else {
-                if ((rc = lead->d_grad_tune.alloc((size_t)3 * lead->n_atoms))) return rc;
-                at.grad = lead->d_grad_tune.p;
-            }
-            // task list the timing launches read: the call's own, or a strided sample of a
-            // large class (kTuneTasks at most)
+            // autotuner: time the kernel variants of each class on this call's task list (of a
+            // batch: the molecule with the most tasks of the class), on a strided sample of at
+            // most kTuneTasks tasks for a large class, into a scratch gradient, and keep the
+            // fastest for later calls.  The wavefront design is a candidate for classes with
+            // >= 27 components, the team designs for every class.  With the mixed route it also
+            // decides the precision per class: the FP32-routed quartets run in FP32 only where
+            // FP64 over the whole class measures slower.
+            int tm_ = 0;
+            DerivArgs at{};
             const int2 *tt = tasks;
-            const int *tm = task_mol;
             // fastest variant of precision pr over the task ranges [b0, e0) and [b1, e1) of tt (the
-            // segments need not be adjacent: the learned veto compacts each in place)
+            // segments need not be adjacent)
             auto best_of = [&](int c, int pr, long long b0, long long e0, long long b1, long long e1, float &best,
                                int &bv) -> int {
                 best = 0.f;
@@ -1735,7 +1764,6 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                             const long long b = k ? b1 : b0, e = merge ? e1 : (k ? e1 : e0);
                             if (e <= b) continue;
                             at.tasks = tt + b;
-                            at.task_mol = tm ? tm + b : nullptr;
                             at.ntasks = e - b;
                             HIP_TRY(kLaunch[c](v, pr, at, lr, st, grid_max));
                         }
@@ -1749,30 +1777,36 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                 return TDG_OK;
             };
             for (int c = 0; c < kNumClasses; ++c) {
-                long long b0 = ch.seg_begin[c][0], e0 = ch.seg_end[c][0];
-                long long b1 = ch.seg_begin[c][1], e1 = ch.seg_end[c][1];
-                if (tuned[c] || (e0 <= b0 && e1 <= b1)) continue;
+                if (tuned[c] || ch.seg_end[c][1] <= ch.seg_begin[c][0]) continue;
                 tuned[c] = true;
+                // the molecule with the most tasks of the class
+                tm_ = 0;
+                long long most = -1;
+                for (int m = 0; m < n; ++m) {
+                    const long long k = (me[m][c][0] - mb[m][c][0]) + (me[m][c][1] - mb[m][c][1]);
+                    if (k > most) { most = k; tm_ = m; }
+                }
+                tdg_plan *pm = pls[tm_];
+                if ((rc = pm->d_grad_tune.alloc((size_t)3 * pm->n_atoms))) return rc;
+                at = margs[tm_];
+                at.grad = pm->d_grad_tune.p;
+                at.task_out = nullptr;
+                long long b0 = mb[tm_][c][0], e0 = me[tm_][c][0], b1 = mb[tm_][c][1], e1 = me[tm_][c][1];
                 tt = tasks;
-                tm = task_mol;
                 const long long n0 = std::max(0LL, e0 - b0), n1 = std::max(0LL, e1 - b1);
                 const long long stride = (n0 + n1 + kTuneTasks - 1) / kTuneTasks;
                 if (stride > 1) {
                     // every stride-th task of each range, the two samples adjacent
                     const long long m0 = (n0 + stride - 1) / stride, m1 = (n1 + stride - 1) / stride;
-                    if ((rc = lead->d_tune_tasks.alloc(m0 + m1)) ||
-                        (task_mol && (rc = lead->d_tune_mol.alloc(m0 + m1))))
-                        return rc;
-                    int *dm = task_mol ? lead->d_tune_mol.p : nullptr;
+                    if ((rc = lead->d_tune_tasks.alloc(m0 + m1))) return rc;
                     if (m0)
                         hipLaunchKernelGGL(k_sample_tasks, dim3((unsigned)((m0 + 255) / 256)), dim3(256), 0, st, tasks,
-                                           task_mol, b0, stride, m0, lead->d_tune_tasks.p, dm);
+                                           nullptr, b0, stride, m0, lead->d_tune_tasks.p, nullptr);
                     if (m1)
                         hipLaunchKernelGGL(k_sample_tasks, dim3((unsigned)((m1 + 255) / 256)), dim3(256), 0, st, tasks,
-                                           task_mol, b1, stride, m1, lead->d_tune_tasks.p + m0, dm ? dm + m0 : nullptr);
+                                           nullptr, b1, stride, m1, lead->d_tune_tasks.p + m0, nullptr);
                     HIP_TRY(hipGetLastError());
                     tt = lead->d_tune_tasks.p;
-                    tm = dm;
                     b0 = 0; e0 = m0; b1 = m0; e1 = m0 + m1;
                 }
                 float t_all = 0.f, t64 = 0.f, t32 = 0.f;
@@ -1792,7 +1826,6 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                 }
             }
             HIP_TRY(hipStreamSynchronize(st));
-            d_targs.release();
         }
         if (det) {
             // every class writes its quartets' twelve values; zeroed first (the wavefront
@@ -1801,27 +1834,69 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             if ((rc = lead->d_tout.alloc(nv))) return rc;
             hipLaunchKernelGGL(k_zero, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, st, lead->d_tout.p, nv);
         }
+        // The class launches of all molecules are independent (each adds into its molecule's
+        // gradient with atomics, or writes its own quartets' values), so they form one launch
+        // graph spread over the plan's streams, which the GPU's hardware queues run side by
+        // side: small classes and small molecules fill the compute units next to the large
+        // ones instead of after them.  Largest expected work first (primitive quartets times
+        // roots times components), each to the stream with the least expected work so far.
+        items.clear();
+        for (int m = 0; m < n; ++m)
+            for (int c = 0; c < kNumClasses; ++c) {
+                if (me[m][c][0] <= mb[m][c][0] && me[m][c][1] <= mb[m][c][1]) continue;
+                int pb, pk;
+                class_pk(c, pb, pk);
+                const int L = kPairL[pb][0] + kPairL[pb][1] + kPairL[pk][0] + kPairL[pk][1];
+                const long long nq = (me[m][c][0] - mb[m][c][0]) + (me[m][c][1] - mb[m][c][1]);
+                const long long nall = chunks.size() == 1 ? nq : cls_count(pls[m], c);
+                const double prim = nall > 0 ? (double)pls[m]->h_prim[c] * nq / nall : 0.0;
+                Item it{m, c, {mb[m][c][0], mb[m][c][1]}, {me[m][c][0], me[m][c][1]},
+                        prim * (L / 2 + 1) * (class_ncomp(c) + 30.0)};
+                items.push_back(it);
+            }
+        std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
+        if ((rc = ensure_item_events(lead, 2 * (int)items.size()))) return rc;
         HIP_TRY(hipEventRecord(lead->ev0, st));
-        for (int c = 0; c < kNumClasses; ++c) {
-            HIP_TRY(hipEventRecord(lead->ev_cls[c], st));
-            // a class that is not split runs its FP32-routed segment with the FP64 kernel:
-            // one launch when the two segments are adjacent, else one per segment (the
-            // learned veto compacts each segment in place)
-            const long long b0 = ch.seg_begin[c][0], e0 = ch.seg_end[c][0];
-            const long long b1 = ch.seg_begin[c][1], e1 = ch.seg_end[c][1];
-            if (!split[c] && e0 == b1) {
-                set_span(a, b0, e1);
-                if (a.ntasks) HIP_TRY(kLaunch[c](variant[0][c], 0, a, lr, st, grid_max));
+        const int nst = lead->nstreams;
+        if (nst > 1) {
+            HIP_TRY(hipEventRecord(lead->ev_fork, st));
+            for (int k = 0; k + 1 < nst; ++k) HIP_TRY(hipStreamWaitEvent(lead->aux[k], lead->ev_fork, 0));
+        }
+        double load[tdg_plan::kMaxAux + 1] = {0.0};
+        for (size_t ii = 0; ii < items.size(); ++ii) {
+            const Item &it = items[ii];
+            const int c = it.c;
+            int k = 0;
+            for (int q = 1; q < nst; ++q)
+                if (load[q] < load[k]) k = q;
+            load[k] += it.cost;
+            hipStream_t sc = k == 0 ? st : lead->aux[k - 1];
+            DerivArgs a = margs[it.m];
+            auto set_span = [&](long long b, long long e) {
+                a.tasks = tasks + b;
+                a.ntasks = e - b;
+                a.task_out = det ? lead->d_tout.p + 12 * b : nullptr;
+            };
+            HIP_TRY(hipEventRecord(lead->ev_item[2 * ii], sc));
+            // a class that is not split runs its FP32-routed range with the FP64 kernel: one
+            // launch when the two ranges are adjacent, else one per range
+            if (!split[c] && it.e[0] == it.b[1]) {
+                set_span(it.b[0], it.e[1]);
+                if (a.ntasks) HIP_TRY(kLaunch[c](variant[0][c], 0, a, lr, sc, grid_max));
             } else {
                 for (int pr = 0; pr < 2; ++pr) {
-                    set_span(a, ch.seg_begin[c][pr], ch.seg_end[c][pr]);
-                    if (!a.ntasks) continue;
+                    set_span(it.b[pr], it.e[pr]);
+                    if (a.ntasks <= 0) continue;
                     const int prec = split[c] ? pr : 0;
-                    HIP_TRY(kLaunch[c](variant[prec][c], prec, a, lr, st, grid_max));
+                    HIP_TRY(kLaunch[c](variant[prec][c], prec, a, lr, sc, grid_max));
                 }
             }
+            HIP_TRY(hipEventRecord(lead->ev_item[2 * ii + 1], sc));
         }
-        HIP_TRY(hipEventRecord(lead->ev_cls[kNumClasses], st));
+        for (int k = 0; k + 1 < nst; ++k) {
+            HIP_TRY(hipEventRecord(lead->ev_join[k], lead->aux[k]));
+            HIP_TRY(hipStreamWaitEvent(st, lead->ev_join[k], 0));
+        }
         if (det) {
             // per-atom sums in a fixed order, segment by segment (a learned veto leaves
             // unused entries between the compacted segments)
@@ -1854,10 +1929,10 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
         if (stats || chunks.size() > 1) {
             // per-chunk timing (the next chunk reuses the event objects)
             HIP_TRY(hipEventSynchronize(lead->ev1));
-            for (int c = 0; c < kNumClasses; ++c) {
+            for (size_t ii = 0; ii < items.size(); ++ii) {
                 float cm = 0.f;
-                HIP_TRY(hipEventElapsedTime(&cm, lead->ev_cls[c], lead->ev_cls[c + 1]));
-                cls_ms[c] += cm;
+                HIP_TRY(hipEventElapsedTime(&cm, lead->ev_item[2 * ii], lead->ev_item[2 * ii + 1]));
+                cls_ms[items[ii].c] += cm;
             }
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, lead->ev0, lead->ev1));

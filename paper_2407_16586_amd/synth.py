@@ -286,6 +286,12 @@ def config2(n_mol: int = 64, with_dens: bool = True) -> list[Molecule]:
             for i, n in enumerate(sizes)]
 
 
+def config2_molecule(i: int, with_dens: bool = True) -> Molecule:
+    """Molecule i of config2() alone (the same seeds, without building the others)."""
+    sizes = np.random.default_rng(BASE_SEED + 2).integers(10, 121, size=64)
+    return droplet(int(sizes[i]), BASE_SEED + 2 + 1000 * (i + 1), with_dens=with_dens)
+
+
 def water_cluster(n_waters: int, seed: int, with_dens: bool = True, recipe: str = "stated") -> Molecule:
     """n waters on the sites of a 6x6x4 cubic lattice (5.9 bohr) nearest its centroid, +-0.4 bohr
     jitter, O-H 1.81 bohr, HOH 104.5 degrees, random orientations; 5 occupied orbitals per water."""

@@ -20,6 +20,8 @@ CASES = {
     "chain60_tau1e-10": dict(mol=synth.config1, tau=1e-10),
     # the same chain with def2-SVP-shaped exponent ranges and positive coefficients
     "chain60svp_tau1e-10": dict(mol=lambda: synth.config1("svp"), tau=1e-10),
+    # molecule 32 of the 64-droplet batch: 61 atoms, 505 Cartesian functions
+    "droplet61_tau1e-10": dict(mol=lambda: synth.config2_molecule(32), tau=1e-10),
 }
 
 
