@@ -185,12 +185,20 @@ def main():
         for _ in range(args.warmup):
             plan.grad_device(P0, PD, R, out, stats=True)
         torch.cuda.synchronize()
-        stats = []
+        # timed steps: the class kernels of a call run side by side on the plan's streams
         t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.grad_device(P0, PD, R, out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        g = out.cpu().numpy().copy()
+        # roofline leg: the same plan and kernels, one stream, so that the HIP events around
+        # each class launch time that kernel alone
+        plan.set_streams(1)
+        stats = []
         for _ in range(args.steps):
             stats.append(plan.grad_device(P0, PD, R, out, stats=True))
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
         st = stats[-1]
         class_ms = np.mean([s["class_ms"] for s in stats], axis=0)
         prims = np.array(st["class_prim_quartets"], dtype=np.float64)
@@ -207,7 +215,6 @@ def main():
         ms_step = 1e3 * dt / args.steps
         achieved = flops[dom] / (class_ms[dom] * 1e-3) / 1e12
         all_tflops = flops.sum() / (class_ms.sum() * 1e-3) / 1e12
-        g = out.cpu().numpy().copy()
         plan.close()
         return {
             "ms_step": ms_step, "plan_s": plan_s, "grad": g, "stats": st, "class_ms": class_ms,
@@ -257,8 +264,8 @@ def main():
         "quartets": head["quartets"],
         "screened_candidates": st["candidates"],
         "prim_quartets": st["prim_quartets"],
-        "kernel_ms": float(head["class_ms"].sum()),
-        "kernel_quartets_per_s": head["quartets"] / (head["class_ms"].sum() * 1e-3),
+        "kernel_ms_one_stream": float(head["class_ms"].sum()),
+        "kernel_quartets_per_s_one_stream": head["quartets"] / (head["class_ms"].sum() * 1e-3),
         "plan_s": head["plan_s"],
         "roofline": head["roofline"],
         "class_ms": {str(c): round(float(m), 4) for c, m in zip(tdgrad.CLASSES, head["class_ms"])},
@@ -270,12 +277,12 @@ def main():
     }
     if fp64:
         rec["fp64"] = {"value": fp64["value"], "wall_s": fp64["ms_step"] * 1e-3,
-                       "kernel_ms": float(fp64["class_ms"].sum()), "roofline_frac": fp64["roofline"]["frac"],
+                       "kernel_ms_one_stream": float(fp64["class_ms"].sum()), "roofline_frac": fp64["roofline"]["frac"],
                        "all_classes_frac": fp64["roofline"]["all_classes_frac"],
                        "max_abs_err_vs_oracle": fp64["err_oracle"]}
     if mixed:
         rec["mixed"] = {"value": mixed["value"], "wall_s": mixed["ms_step"] * 1e-3,
-                        "kernel_ms": float(mixed["class_ms"].sum()),
+                        "kernel_ms_one_stream": float(mixed["class_ms"].sum()),
                         "mixed_tau64": args.mixed_tau64,
                         "mixed_p64": str(args.mixed_p64) if args.mixed_p64 == float("inf") else args.mixed_p64,
                         "fp32_fraction": mixed["stats"]["fp32_quartets"] / max(1, mixed["quartets"]),
@@ -285,7 +292,7 @@ def main():
     if unb:
         rec["mixed_unbounded"] = {
             "note": "tau64 = inf: routed on class timing alone; the error is not bounded by the router",
-            "value": unb["value"], "wall_s": unb["ms_step"] * 1e-3, "kernel_ms": float(unb["class_ms"].sum()),
+            "value": unb["value"], "wall_s": unb["ms_step"] * 1e-3, "kernel_ms_one_stream": float(unb["class_ms"].sum()),
             "fp32_fraction": unb["stats"]["fp32_quartets"] / max(1, unb["quartets"]),
             "max_abs_err_vs_oracle": unb["err_oracle"],
             "speedup_vs_fp64": fp64["ms_step"] / unb["ms_step"] if fp64 else None}

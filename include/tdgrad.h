@@ -266,9 +266,11 @@ int tdg_plan_update_coords(tdg_plan_t *plan, const double *coords);
  * receive them (learned veto not applied).  quartets: host [cap][4] int32, caller shell
  * indices (a, b | c, d) of every stride-th surviving unique quartet (stride >= 1) in the
  * library's canonical orientation (l_a >= l_b, l_c >= l_d, pair class of ab >= that of
- * cd); order: class, then the precision list of the route (FP64, FP32; one list unless
- * the plan is mixed), bra pair, ket pair.  *n_out = the number of survivors (of these
- * at most cap are written).  Densities as in tdg_grad_jk.  Synchronous.
+ * cd).  Order: the list is built in chunks of bra pairs (each holding at most 2^27
+ * survivors; one chunk for all but large systems); within a chunk by class, then the
+ * precision list of the route (FP64, FP32; one list unless the plan is mixed), bra pair,
+ * ket pair.  *n_out = the number of survivors; at most cap are written, and cap = 0 only
+ * counts them.  Densities as in tdg_grad_jk.  Synchronous.
  * Errors: TDG_EINVAL, TDG_ENOMEM, TDG_EDEVICE. */
 int tdg_screen_list(tdg_plan_t *plan, const double *P0, const double *PDelta, const double *R,
                     int32_t ptr_kind, void *hip_stream, int32_t *quartets, int64_t cap, int64_t stride,
@@ -288,6 +290,10 @@ int tdg_quartet_contribs(tdg_plan_t *plan, const double *P0, const double *PDelt
 
 /* Release a plan and its device memory (NULL is accepted). */
 int tdg_plan_destroy(tdg_plan_t *plan);
+
+/* Number of streams the class kernels of later calls spread over: 1 .. the plan's streams
+ * parameter (e.g. 1 to time every kernel alone).  Errors: TDG_EINVAL. */
+int tdg_plan_set_streams(tdg_plan_t *plan, int32_t streams);
 
 /* Number of basis functions and atoms of a plan (for callers sizing buffers). */
 int tdg_plan_dims(const tdg_plan_t *plan, int32_t *n_bf, int32_t *n_atoms, int32_t *n_shells);

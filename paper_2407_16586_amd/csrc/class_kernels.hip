@@ -32,7 +32,19 @@ constexpr int LC = kPL[class_pk(TDG_CLASS)][0], LD = kPL[class_pk(TDG_CLASS)][1]
 constexpr bool kAllRoots = (LA + 1) * (LA + 2) / 2 * ((LB + 1) * (LB + 2) / 2) * ((LC + 1) * (LC + 2) / 2) *
                                ((LD + 1) * (LD + 2) / 2) <= 27;
 
-template <bool LR, typename F, bool BATCH>
+// Blocks for ntasks tasks taken `per` at a time by each block round, at most grid_max: when
+// the tasks need more rounds than one per block, the grid is shrunk so that every block does
+// the same number of rounds (no last round run by a few blocks while the rest of the GPU
+// idles).
+static int grid_for(long long ntasks, long long per, int grid_max)
+{
+    const long long blocks = (ntasks + per - 1) / per;
+    if (blocks <= grid_max) return (int)blocks;
+    const long long rounds = (blocks + grid_max - 1) / grid_max;
+    return (int)((blocks + rounds - 1) / rounds);
+}
+
+template <bool LR, typename F>
 hipError_t go(int variant, const tdg::DerivArgs &a, hipStream_t st, int grid_max)
 {
     using namespace tdg;
@@ -40,16 +52,15 @@ hipError_t go(int variant, const tdg::DerivArgs &a, hipStream_t st, int grid_max
     if constexpr (kAllRoots) {
         if (variant == 3 || variant == 4) {
             using K = DerivClass<LA, LB, LC, LD, LR, F, true>;
-            const long long blocks = (a.ntasks + K::TPB - 1) / K::TPB;
-            const int grid = (int)(blocks < grid_max ? blocks : grid_max);
+            const int grid = grid_for(a.ntasks, K::TPB, grid_max);
             if (variant == 4)
-                hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 2, BATCH, true>), dim3(grid), dim3(K::BLOCK), dyn,
+                hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 2, true>), dim3(grid), dim3(K::BLOCK), dyn,
                                    st, a);
             else if constexpr (sizeof(F) != sizeof(double))
-                hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 1, BATCH, true>), dim3(grid), dim3(K::BLOCK), dyn,
+                hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 1, true>), dim3(grid), dim3(K::BLOCK), dyn,
                                    st, a);
             else
-                hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 0, BATCH, true>), dim3(grid), dim3(K::BLOCK), dyn,
+                hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 0, true>), dim3(grid), dim3(K::BLOCK), dyn,
                                    st, a);
             return hipGetLastError();
         }
@@ -58,60 +69,53 @@ hipError_t go(int variant, const tdg::DerivArgs &a, hipStream_t st, int grid_max
     if (variant == 4) variant = 2;
     if (variant == 0 || variant == 2) {
         using K = DerivClass<LA, LB, LC, LD, LR, F>;
-        const long long blocks = (a.ntasks + K::TPB - 1) / K::TPB;
-        const int grid = (int)(blocks < grid_max ? blocks : grid_max);
+        const int grid = grid_for(a.ntasks, K::TPB, grid_max);
         if (variant == 2)
-            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 2, BATCH>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 2>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
         else if constexpr (sizeof(F) != sizeof(double))
-            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 1, BATCH>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 1>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
         else
-            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 0, BATCH>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+            hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 0>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
     } else {
         using K = WaveClass<LA, LB, LC, LD, LR, F>;
-        const long long blocks = (a.ntasks + K::WAVES - 1) / K::WAVES;
-        const int grid = (int)(blocks < grid_max ? blocks : grid_max);
-        hipLaunchKernelGGL((k_deriv_wave<LA, LB, LC, LD, LR, F, BATCH>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
+        // with four one-wavefront blocks per compute unit holding the whole LDS, the grid is
+        // capped at that many blocks
+        const int grid = grid_for(a.ntasks, K::WAVES, K::BIG ? grid_max / 4 : grid_max);
+        hipLaunchKernelGGL((k_deriv_wave<LA, LB, LC, LD, LR, F>), dim3(grid), dim3(K::BLOCK),
+                           K::ATOMS_LDS ? dyn : 0, st, a);
     }
     return hipGetLastError();
 }
 
 template <bool LR, typename F>
-hipError_t go(int variant, const tdg::DerivArgs &a, hipStream_t st, int grid_max)
-{
-    return a.batch ? go<LR, F, true>(variant, a, st, grid_max) : go<LR, F, false>(variant, a, st, grid_max);
-}
-
-template <bool LR, typename F, bool BATCH>
 const void *kernel_ptr(int variant)
 {
     using namespace tdg;
     if constexpr (kAllRoots) {
-        if (variant == 4) return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 2, BATCH, true>);
+        if (variant == 4) return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 2, true>);
         if (variant == 3) {
             if constexpr (sizeof(F) != sizeof(double))
-                return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 1, BATCH, true>);
+                return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 1, true>);
             else
-                return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 0, BATCH, true>);
+                return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 0, true>);
         }
     }
     if (variant == 3) variant = 0;
     if (variant == 4) variant = 2;
-    if (variant == 1) return reinterpret_cast<const void *>(&k_deriv_wave<LA, LB, LC, LD, LR, F, BATCH>);
-    if (variant == 2) return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 2, BATCH>);
+    if (variant == 1) return reinterpret_cast<const void *>(&k_deriv_wave<LA, LB, LC, LD, LR, F>);
+    if (variant == 2) return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 2>);
     if constexpr (sizeof(F) != sizeof(double))
-        return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 1, BATCH>);
+        return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 1>);
     else
-        return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 0, BATCH>);
+        return reinterpret_cast<const void *>(&k_deriv<LA, LB, LC, LD, LR, F, 0>);
 }
 
 template <bool LR, typename F>
 size_t scratch_of(int variant)
 {
-    hipFuncAttributes a1{}, a2{};
-    if (hipFuncGetAttributes(&a1, kernel_ptr<LR, F, false>(variant)) != hipSuccess ||
-        hipFuncGetAttributes(&a2, kernel_ptr<LR, F, true>(variant)) != hipSuccess)
-        return (size_t)-1;
-    return a1.localSizeBytes > a2.localSizeBytes ? a1.localSizeBytes : a2.localSizeBytes;
+    hipFuncAttributes a1{};
+    if (hipFuncGetAttributes(&a1, kernel_ptr<LR, F>(variant)) != hipSuccess) return (size_t)-1;
+    return a1.localSizeBytes;
 }
 } // namespace
 

@@ -22,10 +22,6 @@ struct DerivArgs {
     int n_atoms;
     int lds_atoms;          // 1: block-level accumulation in LDS (dynamic shared memory)
     double *task_out;       // optional per-task output [ntasks][12] (canonical centres)
-    // batched launch over many molecules: per-task molecule index and per-molecule
-    // argument blocks (their own tables, densities and gradient); null for one molecule
-    const int *task_mol;
-    const DerivArgs *batch;
 };
 
 // 2D Rys integrals for one root and one Cartesian direction.
@@ -315,11 +311,9 @@ __device__ __forceinline__ void pair_records(int n_bf, int oa, int ob, int oc, i
 // (double, or float for the mixed-precision route); roots, weights, prefactors and
 // the running sums are FP64 in both.  MODE 0: vertical recursion plus transfers
 // (FP64 only); 1: derivative tables from the direct four-centre recurrence; 2: the
-// direct base tables with the collapsed contraction (collapse_sums).  BATCH: tasks of
-// many molecules, each with its own argument block (a.batch[a.task_mol[t]]); without it
-// every table pointer comes from the kernel arguments.  ALLR: each lane evaluates all
-// roots of its range (see DerivClass).
-template <int LA, int LB, int LC, int LD, bool LR, typename F, int MODE, bool BATCH, bool ALLR = false>
+// direct base tables with the collapsed contraction (collapse_sums).  ALLR: each lane
+// evaluates all roots of its range (see DerivClass).
+template <int LA, int LB, int LC, int LD, bool LR, typename F, int MODE, bool ALLR = false>
 __global__ void __launch_bounds__((DerivClass<LA, LB, LC, LD, LR, F, ALLR>::BLOCK))
 k_deriv(const DerivArgs a)
 {
@@ -357,42 +351,15 @@ k_deriv(const DerivArgs a)
         __syncthreads();
     }
     const double iom2 = LR ? 1.0 / (a.omega * a.omega) : 0.0;
+    // blocks take rounds of TPB consecutive tasks at a fixed grid stride (the host sizes the
+    // grid so that every block does the same number of rounds); consecutive blocks run on
+    // different XCDs, so every XCD gets an even share of each stretch of the task list
     const long long stride = (long long)gridDim.x * TPB;
-    // batched launches: the LDS array holds the gradient of molecule cur (the molecule of
-    // the block's first task); it is flushed when the block moves on to another molecule
-    // (tasks are molecule-major within a class, so that is rare), and tasks of other
-    // molecules inside a block's range go straight to their global gradient
-    int cur = -1;
-    auto flush_mol = [&](int m) {
-        const int n3 = 3 * a.batch[m].n_atoms;
-        double *g = a.batch[m].grad;
-        for (int i = tid; i < n3; i += blockDim.x) {
-            const double v = s_atoms[i];
-            if (v != 0.0) atomic_add_global(&g[i], v);
-            s_atoms[i] = 0.0;
-        }
-    };
     for (long long base = (long long)blockIdx.x * TPB; base < a.ntasks; base += stride) {
-        if constexpr (BATCH) {
-            const int m0 = a.task_mol[base];
-            if (a.lds_atoms && m0 != cur) { // block-uniform
-                // LDS operations of different wavefronts are not ordered by the barrier
-                // alone: every wavefront's pending LDS additions (issued without return at
-                // the end of the previous task) must land before the array is read, and
-                // the zeros before the next task adds to it
-                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-                __syncthreads();
-                if (cur >= 0) flush_mol(cur);
-                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-                __syncthreads();
-                cur = m0;
-            }
-        }
         const long long t = base + team;
         const bool valid = lane_ok && t < a.ntasks;
         int bra = 0, ket = 0, sa = 0, sb = 0, sc = 0, sd = 0;
-        const int tmol = BATCH && valid ? a.task_mol[t] : 0;
-        const DerivArgs &M = BATCH ? a.batch[tmol] : a;
+        const DerivArgs &M = a;
         if (valid) {
             const int2 tk = a.tasks[t];
             bra = tk.x;
@@ -657,7 +624,7 @@ k_deriv(const DerivArgs a)
                 for (int X = 0; X < 4; ++X)
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
-                        if (a.lds_atoms && (!BATCH || tmol == cur)) atomicAdd(&s_atoms[3 * at[X] + d], out[3 * X + d]);
+                        if (a.lds_atoms) atomicAdd(&s_atoms[3 * at[X] + d], out[3 * X + d]);
                         else atomic_add_global(&M.grad[3 * at[X] + d], out[3 * X + d]);
                     }
             }
@@ -665,14 +632,13 @@ k_deriv(const DerivArgs a)
         wave_sync();
     }
     if (a.lds_atoms) {
+        // every wavefront's LDS additions (issued without return) land before the array is
+        // read: the barrier alone does not order LDS operations of different wavefronts
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         __syncthreads();
-        if constexpr (BATCH) {
-            if (cur >= 0) flush_mol(cur);
-        } else {
-            for (int i = tid; i < 3 * a.n_atoms; i += blockDim.x) {
-                const double v = s_atoms[i];
-                if (v != 0.0) atomic_add_global(&a.grad[i], v);
-            }
+        for (int i = tid; i < 3 * a.n_atoms; i += blockDim.x) {
+            const double v = s_atoms[i];
+            if (v != 0.0) atomic_add_global(&a.grad[i], v);
         }
     }
 }

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -1220,6 +1221,18 @@ int tdg_plan_destroy(tdg_plan_t *pl)
     return TDG_OK;
 }
 
+int tdg_plan_set_streams(tdg_plan_t *pl, int32_t streams)
+{
+    g_err.clear();
+    if (!pl) return fail(TDG_EINVAL, "null plan");
+    int avail = 1;
+    while (avail <= tdg_plan::kMaxAux && pl->aux[avail - 1]) ++avail;
+    if (streams < 1 || streams > avail)
+        return fail(TDG_EINVAL, "streams must be 1..%d for this plan", avail);
+    pl->nstreams = streams;
+    return TDG_OK;
+}
+
 int tdg_plan_dims(const tdg_plan_t *pl, int32_t *n_bf, int32_t *n_atoms, int32_t *n_shells)
 {
     if (!pl) return fail(TDG_EINVAL, "null plan");
@@ -1535,6 +1548,13 @@ static void region_counts(tdg_plan *pl)
     }
 }
 
+// TDG_PROGRESS set in the environment: a line on stderr after every task-list chunk of a call
+static bool progress_lines()
+{
+    static const bool on = std::getenv("TDG_PROGRESS") != nullptr;
+    return on;
+}
+
 // timing events for n class-kernel items (created once, kept by the plan)
 static int ensure_item_events(tdg_plan *pl, int n)
 {
@@ -1652,10 +1672,13 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                     me[0][c][pr] = ch.seg_end[c][pr];
                 }
         } else {
+            // offsets of this chunk's items only: entry k - i0 of molecule m's vectors, with
+            // [i0, i1) the chunk's items (all items of every molecule in a batch)
             std::vector<std::vector<long long>> offs(n), offs32(n);
             for (int m = 0; m < n; ++m) {
-                offs[m].assign(pls[m]->item_class_off[kNumClasses], 0);
-                offs32[m].assign(pls[m]->item_class_off[kNumClasses], 0);
+                const int i0 = batched ? 0 : K0, i1 = batched ? pls[m]->item_class_off[kNumClasses] : K1;
+                offs[m].assign(std::max(i1 - i0, 1), 0);
+                offs32[m].assign(std::max(i1 - i0, 1), 0);
             }
             long long total = 0;
             for (int c = 0; c < kNumClasses; ++c)
@@ -1664,11 +1687,12 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                     for (int m = 0; m < n; ++m) {
                         tdg_plan *pl = pls[m];
                         const bool act = class_active(pl, c);
+                        const int i0 = batched ? 0 : K0;
                         int lo = pl->item_class_off[c], hi = pl->item_class_off[c + 1];
                         if (!batched) { lo = std::max(lo, K0); hi = std::min(hi, K1); }
                         mb[m][c][pr] = total;
                         for (int k = lo; k < hi; ++k) {
-                            if (pr == 0) offs[m][k] = total; else offs32[m][k] = total;
+                            if (pr == 0) offs[m][k - i0] = total; else offs32[m][k - i0] = total;
                             if (act) total += pr == 0 ? pl->h_cnt[k] : pl->h_cnt32[k];
                         }
                         me[m][c][pr] = total;
@@ -1690,10 +1714,10 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                 tdg_plan *pl = pls[m];
                 const int i0 = batched ? 0 : K0, i1 = batched ? pl->item_class_off[kNumClasses] : K1;
                 if (i1 > i0) {
-                    HIP_TRY(hipMemcpyAsync(pl->d_item_off.p + i0, offs[m].data() + i0, 8 * (i1 - i0),
+                    HIP_TRY(hipMemcpyAsync(pl->d_item_off.p + i0, offs[m].data(), 8 * (i1 - i0),
                                            hipMemcpyHostToDevice, st));
                     if (pl->prm.precision == 1)
-                        HIP_TRY(hipMemcpyAsync(pl->d_item_off32.p + i0, offs32[m].data() + i0, 8 * (i1 - i0),
+                        HIP_TRY(hipMemcpyAsync(pl->d_item_off32.p + i0, offs32[m].data(), 8 * (i1 - i0),
                                                hipMemcpyHostToDevice, st));
                 }
                 ScreenArgs s = screen_args(pl);
@@ -1926,6 +1950,13 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             tot_quartets += n64 + n32;
             tot_fp32 += split[c] ? n32 : 0;
         }
+        if (progress_lines()) {
+            HIP_TRY(hipEventSynchronize(lead->ev1));
+            fprintf(stderr, "tdgrad: chunk %zu of %zu done, %lld quartets so far, %.1f s\n", ci + 1, chunks.size(),
+                    tot_quartets,
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
+            fflush(stderr);
+        }
         if (stats || chunks.size() > 1) {
             // per-chunk timing (the next chunk reuses the event objects)
             HIP_TRY(hipEventSynchronize(lead->ev1));
@@ -2147,22 +2178,21 @@ int tdg_collect(tdg_plan_t *pl, const double *P0, const double *PD, const double
 // ----------------------------------------------------------------------------------
 // Verification entry points and geometry updates.
 
-// count and fill passes for all classes of one molecule into pl->d_tasks (no chunking):
-// per class the FP64-routed list, then the FP32-routed list (mixed plans)
-static int two_pass_tasks(tdg_plan *pl, hipStream_t st, Chunk &ch)
+// fill pass for the screening items [K0, K1) of one molecule into pl->d_tasks (after a count
+// pass): per class the FP64-routed list, then the FP32-routed list (mixed plans)
+static int fill_items(tdg_plan *pl, hipStream_t st, int K0, int K1, Chunk &ch)
 {
     int rc;
-    if ((rc = count_pass(pl, st))) return rc;
-    HIP_TRY(hipStreamSynchronize(st));
-    const int nitems = pl->item_class_off[kNumClasses];
-    std::vector<long long> offs(std::max(nitems, 1), 0), offs32(std::max(nitems, 1), 0);
+    // offsets of the items [K0, K1) only (a large system has tens of millions of items)
+    std::vector<long long> offs(std::max(K1 - K0, 1), 0), offs32(std::max(K1 - K0, 1), 0);
     long long total = 0;
     for (int c = 0; c < kNumClasses; ++c) {
         const bool act = class_active(pl, c);
+        const int lo = std::max(pl->item_class_off[c], K0), hi = std::min(pl->item_class_off[c + 1], K1);
         for (int pr = 0; pr < 2; ++pr) {
             ch.seg_begin[c][pr] = total;
-            for (int k = pl->item_class_off[c]; k < pl->item_class_off[c + 1]; ++k) {
-                (pr ? offs32 : offs)[k] = total;
+            for (int k = lo; k < hi; ++k) {
+                (pr ? offs32 : offs)[k - K0] = total;
                 if (act) total += pr ? pl->h_cnt32[k] : pl->h_cnt[k];
             }
             ch.seg_end[c][pr] = total;
@@ -2170,15 +2200,18 @@ static int two_pass_tasks(tdg_plan *pl, hipStream_t st, Chunk &ch)
     }
     ch.total = total;
     if ((rc = pl->d_tasks.alloc(std::max<long long>(total, 1)))) return rc;
-    if (nitems) {
-        HIP_TRY(hipMemcpyAsync(pl->d_item_off.p, offs.data(), 8 * nitems, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(pl->d_item_off32.p, offs32.data(), 8 * nitems, hipMemcpyHostToDevice, st));
+    if (K1 > K0) {
+        HIP_TRY(hipMemcpyAsync(pl->d_item_off.p + K0, offs.data(), 8 * (K1 - K0), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(pl->d_item_off32.p + K0, offs32.data(), 8 * (K1 - K0), hipMemcpyHostToDevice, st));
     }
     ScreenArgs s = screen_args(pl);
     s.tasks = pl->d_tasks.p;
     ScreenTable t{};
-    for (int c = 0; c < kNumClasses; ++c)
-        if (class_active(pl, c)) screen_add(pl, t, c);
+    for (int c = 0; c < kNumClasses; ++c) {
+        if (!class_active(pl, c)) continue;
+        const int lo = std::max(pl->item_class_off[c], K0), hi = std::min(pl->item_class_off[c + 1], K1);
+        if (hi > lo) screen_add(pl, t, c, lo - pl->item_class_off[c], hi - lo);
+    }
     screen_launch<1>(s, t, st);
     HIP_TRY(hipGetLastError());
     // the offsets are read by the fill pass before the host vectors go out of scope
@@ -2252,28 +2285,62 @@ int tdg_screen_list(tdg_plan_t *pl, const double *P0, const double *PD, const do
     hipStream_t st = (hipStream_t)hip_stream;
     HIP_TRY(hipSetDevice(pl->device));
     int rc;
-    Chunk ch;
-    if ((rc = prep_density(pl, P0, PD, R, ptr_kind, st)) || (rc = two_pass_tasks(pl, st, ch))) return rc;
-    const long long nw = std::min<long long>((ch.total + stride - 1) / stride, cap);
-    if (nw > 0) {
-        // the sampled tasks, gathered on the device (every stride-th one)
-        DevBuf<int2> d_s;
-        if ((rc = d_s.alloc(nw))) return rc;
-        hipLaunchKernelGGL(k_sample_tasks, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, pl->d_tasks.p,
-                           nullptr, 0LL, (long long)stride, nw, d_s.p, nullptr);
-        std::vector<int2> h(nw);
-        const hipError_t e = hipMemcpyAsync(h.data(), d_s.p, sizeof(int2) * nw, hipMemcpyDeviceToHost, st);
-        const hipError_t e2 = e == hipSuccess ? hipStreamSynchronize(st) : e;
-        d_s.release();
-        if (e2 != hipSuccess) return fail(TDG_EDEVICE, "survivor copy failed: %s", hipGetErrorString(e2));
-        for (long long k = 0; k < nw; ++k) {
-            quartets[4 * k] = pl->pair_sa[h[k].x];
-            quartets[4 * k + 1] = pl->pair_sb[h[k].x];
-            quartets[4 * k + 2] = pl->pair_sa[h[k].y];
-            quartets[4 * k + 3] = pl->pair_sb[h[k].y];
+    if ((rc = prep_density(pl, P0, PD, R, ptr_kind, st)) || (rc = count_pass(pl, st))) return rc;
+    HIP_TRY(hipStreamSynchronize(st));
+    const int nitems = pl->item_class_off[kNumClasses];
+    long long total = 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+        if (!class_active(pl, c)) continue;
+        for (int k = pl->item_class_off[c]; k < pl->item_class_off[c + 1]; ++k)
+            total += (long long)pl->h_cnt[k] + pl->h_cnt32[k];
+    }
+    *n_out = total;
+    // the list is filled in chunks of bra pairs holding at most kListChunk quartets, and
+    // every stride-th quartet (in the order of the chunks) is kept
+    constexpr long long kListChunk = 1LL << 27;
+    long long written = 0, seen = 0;
+    int K0 = 0;
+    while (K0 < nitems && written < cap) {
+        int K1 = K0;
+        long long acc = 0;
+        for (int c = 0; K1 < nitems; ++K1) {
+            while (K1 >= pl->item_class_off[c + 1]) ++c;
+            const long long v = class_active(pl, c) ? (long long)pl->h_cnt[K1] + pl->h_cnt32[K1] : 0;
+            if (acc + v > kListChunk && K1 > K0) break;
+            acc += v;
+        }
+        Chunk ch;
+        if ((rc = fill_items(pl, st, K0, K1, ch))) return rc;
+        const long long L = ch.total;
+        const long long j0 = (stride - seen % stride) % stride;
+        long long m = L > j0 ? (L - j0 + stride - 1) / stride : 0;
+        m = std::min<long long>(m, cap - written);
+        if (m > 0) {
+            DevBuf<int2> d_s;
+            if ((rc = d_s.alloc(m))) return rc;
+            hipLaunchKernelGGL(k_sample_tasks, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, pl->d_tasks.p,
+                               nullptr, j0, (long long)stride, m, d_s.p, nullptr);
+            std::vector<int2> h(m);
+            const hipError_t e = hipMemcpyAsync(h.data(), d_s.p, sizeof(int2) * m, hipMemcpyDeviceToHost, st);
+            const hipError_t e2 = e == hipSuccess ? hipStreamSynchronize(st) : e;
+            d_s.release();
+            if (e2 != hipSuccess) return fail(TDG_EDEVICE, "survivor copy failed: %s", hipGetErrorString(e2));
+            for (long long k = 0; k < m; ++k) {
+                int32_t *q = quartets + 4 * (written + k);
+                q[0] = pl->pair_sa[h[k].x];
+                q[1] = pl->pair_sb[h[k].x];
+                q[2] = pl->pair_sa[h[k].y];
+                q[3] = pl->pair_sb[h[k].y];
+            }
+            written += m;
+        }
+        seen += L;
+        K0 = K1;
+        if (progress_lines()) {
+            fprintf(stderr, "tdgrad: survivor list, %lld of %lld quartets listed, %lld kept\n", seen, total, written);
+            fflush(stderr);
         }
     }
-    *n_out = ch.total;
     return TDG_OK;
 }
 

@@ -23,7 +23,7 @@ CLASSES = tuple(PAIR_CLASSES[b] + PAIR_CLASSES[k] for b in range(6) for k in ran
 
 EXPORTED = ("tdg_plan_create", "tdg_grad_jk", "tdg_grad_jk_batch", "tdg_plan_destroy", "tdg_plan_dims",
             "tdg_plan_schwarz", "tdg_rys_rule", "tdg_plan_set_screen_model", "tdg_collect",
-            "tdg_plan_update_coords", "tdg_screen_list", "tdg_quartet_contribs", "tdg_grad_jk_noalloc",
+            "tdg_plan_update_coords", "tdg_screen_list", "tdg_quartet_contribs", "tdg_grad_jk_noalloc", "tdg_plan_set_streams",
             "tdg_mlp_create", "tdg_mlp_destroy", "tdg_mlp_nweights", "tdg_mlp_set_weights",
             "tdg_mlp_get_weights", "tdg_mlp_forward", "tdg_mlp_grad", "tdg_mlp_train_step",
             "tdg_last_error")
@@ -100,6 +100,7 @@ def lib():
                                   C.POINTER(C.c_int64)]
         L.tdg_grad_jk_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(Stats)]
         L.tdg_plan_update_coords.argtypes = [vp, vp]
+        L.tdg_plan_set_streams.argtypes = [vp, C.c_int32]
         L.tdg_screen_list.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, C.c_int64, C.c_int64,
                                       C.POINTER(C.c_int64)]
         L.tdg_quartet_contribs.argtypes = [vp, vp, vp, vp, C.c_int32, vp, C.c_int64, vp, C.c_int32, vp]
@@ -181,6 +182,10 @@ class Plan:
         _check(lib().tdg_grad_jk(self._h, _ptr(P0), _ptr(PD), _ptr(R), 0, None, _ptr(out),
                                  C.byref(st) if stats else None))
         return (out, st.as_dict()) if stats else out
+
+    def set_streams(self, n):
+        """Spread the class kernels of later calls over n streams (1 .. the plan's streams)."""
+        _check(lib().tdg_plan_set_streams(self._h, int(n)))
 
     def update_coords(self, coords):
         """Move the plan to new coordinates [n_atoms, 3] (bohr); see tdg_plan_update_coords."""

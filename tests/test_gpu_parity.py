@@ -79,7 +79,7 @@ def test_config0_screened(tdg, oracle_lib, mol0):
     p = tdg.Plan(mol0, schwarz_tol=1e-10)
     g, st = p.grad(mol0.P0, mol0.PD, mol0.R, stats=True)
     ref, rst = oracle_lib.grad(mol0, tau=1e-10, return_stats=True)
-    assert abs(st["quartets"] - rst["quartets"]) <= 2
+    assert st["quartets"] == rst["quartets"] and st["prim_quartets"] == rst["prim_quartets"]
     assert np.abs(g - ref).max() <= TOL
 
 
@@ -160,7 +160,8 @@ def test_chain60_against_stored_oracle(tdg, variant):
     g, st = p.grad(m.P0, m.PD, m.R, stats=True)
     err = np.abs(g - np.array(ref["grad"])).max()
     _say("chain60 max-abs", err, "quartets", st["quartets"], ref["oracle_stats"]["quartets"])
-    assert abs(st["quartets"] - ref["oracle_stats"]["quartets"]) <= 0.0001 * ref["oracle_stats"]["quartets"]
+    assert st["quartets"] == ref["oracle_stats"]["quartets"]
+    assert st["prim_quartets"] == ref["oracle_stats"]["prim_quartets"]
     assert err <= TOL
 
 
@@ -257,8 +258,31 @@ def test_chain60_svp_against_stored_oracle(tdg, precision, tau64):
     g, st = p.grad(m.P0, m.PD, m.R, stats=True)
     err = np.abs(g - np.array(ref["grad"])).max()
     _say("chain60svp", precision, "max-abs", err, "quartets", st["quartets"], ref["oracle_stats"]["quartets"])
-    assert abs(st["quartets"] - ref["oracle_stats"]["quartets"]) <= 0.0001 * ref["oracle_stats"]["quartets"]
+    assert st["quartets"] == ref["oracle_stats"]["quartets"]
     assert err <= (TOL if precision == 0 else MIXED_TOL)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_droplet61_against_stored_oracle(tdg, precision):
+    """Molecule 32 of the 64-droplet batch (61 atoms, 505 functions, 46.4M surviving quartets)
+    against the oracle's stored gradient, alone and inside a batch of four molecules."""
+    from paper_2407_16586_amd import synth
+    ref = json.load(open(os.path.join(HERE, "golden", "droplet61_tau1e-10.json")))
+    m = synth.config2_molecule(32)
+    tol = TOL if precision == 0 else MIXED_TOL
+    p = tdg.Plan(m, schwarz_tol=ref["tau"], precision=precision)
+    g, st = p.grad(m.P0, m.PD, m.R, stats=True)
+    err = np.abs(g - np.array(ref["grad"])).max()
+    _say("droplet61", precision, "max-abs", err, "quartets", st["quartets"], ref["oracle_stats"]["quartets"])
+    assert st["quartets"] == ref["oracle_stats"]["quartets"]
+    assert err <= tol
+    others = [synth.config2_molecule(i) for i in (3, 17, 40)]
+    mols = [others[0], m] + others[1:]
+    plans = [tdg.Plan(x, schwarz_tol=ref["tau"], precision=precision) for x in mols]
+    outs = tdg.grad_batch(plans, [(x.P0, x.PD, x.R) for x in mols])
+    err_b = np.abs(outs[1] - np.array(ref["grad"])).max()
+    _say("  in a batch of 4", err_b)
+    assert err_b <= tol
 
 
 @pytest.mark.parametrize("precision", [0, 1])
