@@ -71,6 +71,23 @@ def _traffic(cls, variant, prec, nq):
     return None
 
 
+def _executed_flops(cls, variant, prec, nq):
+    """Executed floating-point operations per launch of one class kernel from the committed
+    instruction-counter summaries (64 lanes x (2 FMA + ADD + MUL + TRANS) per wavefront
+    instruction, FP64 and FP32), or None when none was taken on the current sources for a
+    launch of the same number of quartets."""
+    import glob
+    sha, key = _sources_sha(), "".join(map(str, cls))
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_flops.txt"))):
+        with open(path) as fh:
+            for line in fh:
+                f = line.split()
+                if len(f) >= 8 and f[0] == "flops" and f[1] == key and f[2] == str(variant) and f[3] == prec \
+                        and f[4] == sha and f[7] == str(nq):
+                    return int(f[5]), int(f[6])
+    return None
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -152,6 +169,9 @@ def main():
                     help="mixed path: pairs with a primitive exponent sum at or above this stay in FP64")
     ap.add_argument("--no-unbounded", action="store_true",
                     help="skip the secondary mixed leg that routes on class timing alone (tau64 = inf)")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="streams the class kernels of a timed call run on (0 = the library's default, 4); "
+                         "profiling runs use 1 so that every kernel is timed alone")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy MIB MiB device-to-device (a plain copy of known "
                          "size that calibrates the HBM counters of a profiling run)")
@@ -179,7 +199,8 @@ def main():
     def run_path(precision, tau64=args.mixed_tau64, p64=args.mixed_p64):
         print(f"bench: plan for {mol.name}, precision {precision}", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
-        plan = tdgrad.Plan(mol, schwarz_tol=1e-10, precision=precision, mixed_tau64=tau64, mixed_p64=p64)
+        plan = tdgrad.Plan(mol, schwarz_tol=1e-10, precision=precision, mixed_tau64=tau64, mixed_p64=p64,
+                           streams=args.streams)
         plan_s = time.perf_counter() - t0
         out = torch.zeros((mol.n_atoms, 3), dtype=torch.float64, device=dev)
         for _ in range(args.warmup):
@@ -215,6 +236,9 @@ def main():
         ms_step = 1e3 * dt / args.steps
         achieved = flops[dom] / (class_ms[dom] * 1e-3) / 1e12
         all_tflops = flops.sum() / (class_ms.sum() * 1e-3) / 1e12
+        nq_dom = launch_quartets(st, dom, dprec)
+        ex = _executed_flops(tdgrad.CLASSES[dom], dvar, dprec, nq_dom)
+        executed = (ex[0] + ex[1]) / (class_ms[dom] * 1e-3) / 1e12 if ex else None
         plan.close()
         return {
             "ms_step": ms_step, "plan_s": plan_s, "grad": g, "stats": st, "class_ms": class_ms,
@@ -224,7 +248,11 @@ def main():
                          "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / FP64_VALU_PEAK_TFLOPS,
                          "traffic": _traffic(tdgrad.CLASSES[dom], dvar, dprec, launch_quartets(st, dom, dprec)),
-                         "launch_quartets": launch_quartets(st, dom, dprec),
+                         "launch_quartets": nq_dom,
+                         "launch_prim_quartets": int(prims[dom]) if not (cv & 64) or n32 == 0 else None,
+                         "flop_per_prim_quartet": int(FLOPS_PER_PRIM[tdgrad.CLASSES[dom]]),
+                         "executed": executed,
+                         "executed_frac": executed / FP64_VALU_PEAK_TFLOPS if executed else None,
                          "all_classes_achieved": all_tflops,
                          "all_classes_frac": all_tflops / FP64_VALU_PEAK_TFLOPS},
         }

@@ -133,6 +133,9 @@ typedef struct {
                               order (fixed blocks of tasks, then the blocks in order) instead of by
                               floating-point atomics.  Slower; single-molecule calls of a batch run
                               one after another.  0: atomics (default) */
+    int32_t ml_min_components; /* screening = 1: the learned veto applies only to classes with at
+                                  least this many Cartesian components (their quartets cost far
+                                  more than one network evaluation); 0 = every class */
     int32_t streams;    /* the class kernels of a call run side by side on this many HIP streams
                            (the caller's stream and streams - 1 of the plan's, joined back into
                            the caller's stream before the call's last step); 1 = all on the

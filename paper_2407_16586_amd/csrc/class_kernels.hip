@@ -78,11 +78,8 @@ hipError_t go(int variant, const tdg::DerivArgs &a, hipStream_t st, int grid_max
             hipLaunchKernelGGL((k_deriv<LA, LB, LC, LD, LR, F, 0>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
     } else {
         using K = WaveClass<LA, LB, LC, LD, LR, F>;
-        // with four one-wavefront blocks per compute unit holding the whole LDS, the grid is
-        // capped at that many blocks
-        const int grid = grid_for(a.ntasks, K::WAVES, K::BIG ? grid_max / 4 : grid_max);
-        hipLaunchKernelGGL((k_deriv_wave<LA, LB, LC, LD, LR, F>), dim3(grid), dim3(K::BLOCK),
-                           K::ATOMS_LDS ? dyn : 0, st, a);
+        const int grid = grid_for(a.ntasks, K::WAVES, grid_max);
+        hipLaunchKernelGGL((k_deriv_wave<LA, LB, LC, LD, LR, F>), dim3(grid), dim3(K::BLOCK), dyn, st, a);
     }
     return hipGetLastError();
 }

@@ -27,22 +27,13 @@ struct WaveClass {
     static constexpr int NBASE = (LA + 1) * (LB + 1) * (LC + 1) * (LD + 1);
     static constexpr int TAB = 12 * NBASE;               // doubles per slot (3 dirs x 4 kinds)
     static constexpr int FB = (int)sizeof(F);
-    // The classes with >= 216 components hold enough per-lane state (Gamma of 4 or more
-    // components, table offsets, the recurrence) that registers allow one wavefront per
-    // SIMD; their wavefronts then take 36 KB of LDS each (four per compute unit), so that
-    // stage 1 builds the tables of several root slots at once instead of one, and they add
-    // their gradient contributions straight to global memory.  The other classes keep
-    // 14 KB per wavefront, four wavefronts per block and the per-block LDS gradient.
-    static constexpr bool BIG = N >= 216;
-    static constexpr int LDS_WAVE = BIG ? 36 * 1024 : 14 * 1024;
-    static constexpr int CH_LDS = LDS_WAVE / (TAB * FB) > 0 ? LDS_WAVE / (TAB * FB) : 1;
+    static constexpr int CH_LDS = (14 * 1024) / (TAB * FB) > 0 ? (14 * 1024) / (TAB * FB) : 1;
     static constexpr int CH0 = CH_LDS < NSLOT ? CH_LDS : NSLOT;
     static constexpr int CH = CH0 * 3 <= kWave ? CH0 : kWave / 3;
     static constexpr int NCHUNK = (NSLOT + CH - 1) / CH;
     static constexpr int WAVE_LDS = CH * TAB;            // elements per wave
-    static constexpr int WAVES = BIG ? 1 : (WAVE_LDS * FB * 4 <= 64 * 1024 ? 4 : 2);
+    static constexpr int WAVES = WAVE_LDS * FB * 4 <= 64 * 1024 ? 4 : 2;
     static constexpr int BLOCK = WAVES * kWave;
-    static constexpr bool ATOMS_LDS = !BIG;              // per-block gradient in LDS
     static constexpr int CPL = (N + kWave - 1) / kWave;  // components per lane
     static constexpr bool EARLY_PREFETCH = N <= 27;      // next ket record loaded ahead
 };
@@ -59,8 +50,8 @@ k_deriv_wave(const DerivArgs a)
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     F *tab = s_tab + wave * K::WAVE_LDS;
-    // block-level accumulation in LDS (classes with small tables)
-    const bool use_lds = a.lds_atoms && K::ATOMS_LDS;
+    // block-level accumulation in LDS
+    const bool use_lds = a.lds_atoms;
     if (use_lds) {
         for (int i = tid; i < 3 * a.n_atoms; i += blockDim.x) s_atoms[i] = 0.0;
         __syncthreads();

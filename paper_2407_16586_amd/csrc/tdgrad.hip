@@ -1153,6 +1153,7 @@ int tdg_plan_create(const tdg_basis_t *basis, const tdg_params_t *params, int de
         return fail(TDG_EINVAL, "deterministic must be 0 or 1");
     if (params->max_tasks < 0) return fail(TDG_EINVAL, "max_tasks must be >= 0");
     if (params->streams < 0) return fail(TDG_EINVAL, "streams must be >= 0");
+    if (params->ml_min_components < 0) return fail(TDG_EINVAL, "ml_min_components must be >= 0");
     int ndev = 0;
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(TDG_EINVAL, "device %d not present (%d devices)", device, ndev);
@@ -1395,6 +1396,11 @@ static int ml_filter(tdg_plan *pl, int2 *&tasks, long long (*seg_begin)[2], long
                 hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (double *)(pl->d_segcnt.p + 2 * c + pr), 1LL);
                 continue;
             }
+            if (class_ncomp(c) < pl->prm.ml_min_components) {
+                // a class whose quartets cost less than the network: kept whole
+                HIP_TRY(hipMemcpyAsync(pl->d_tasks2.p + b, tasks + b, sizeof(int2) * n, hipMemcpyDeviceToDevice, st));
+                continue;
+            }
             const int grid = (int)std::min<long long>((n + 255) / 256, 8192);
             hipLaunchKernelGGL(k_ml_filter, dim3(grid), dim3(256), 0, st, tasks + b, n, f, w, w1b, w2b, thr,
                                pl->ml_tau_hi, pl->d_keep.p + b);
@@ -1415,7 +1421,7 @@ static int ml_filter(tdg_plan *pl, int2 *&tasks, long long (*seg_begin)[2], long
     for (int c = 0; c < kNumClasses; ++c)
         for (int pr = 0; pr < 2; ++pr) {
             const long long n = seg_end[c][pr] - seg_begin[c][pr];
-            const long long k = n ? cnt[2 * c + pr] : 0;
+            const long long k = !n ? 0 : (class_ncomp(c) < pl->prm.ml_min_components ? n : cnt[2 * c + pr]);
             skipped += n - k;
             seg_end[c][pr] = seg_begin[c][pr] + k;
         }

@@ -100,3 +100,11 @@ def schwarz_only(mol, ref, tol=1e-6, taus=(1e-7, 3e-8, 1e-8, 3e-9, 1e-9, 3e-10, 
         if err <= tol:
             return tau, err, st
     return None, None, None
+
+
+def budget_threshold(n_quartets, budget=1e-6, margin=1.0):
+    """Veto threshold (log10 of a quartet's largest contribution) from an error budget that
+    scales with the system: n vetoed contributions of random sign below t add up to about
+    t sqrt(n), so t = budget / sqrt(n), lowered by `margin` decades for the estimator's own
+    error."""
+    return float(np.log10(budget) - 0.5 * np.log10(max(n_quartets, 1)) - margin)

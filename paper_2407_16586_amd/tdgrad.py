@@ -48,7 +48,8 @@ class Params(C.Structure):
                 ("schwarz_tol", C.c_double), ("precision", C.c_int32), ("terms", C.c_int32),
                 ("autotune", C.c_int32), ("kernel_variant", C.c_int32),
                 ("mixed_tau64", C.c_double), ("mixed_p64", C.c_double), ("max_tasks", C.c_int64),
-                ("screening", C.c_int32), ("deterministic", C.c_int32), ("streams", C.c_int32)]
+                ("screening", C.c_int32), ("deterministic", C.c_int32), ("ml_min_components", C.c_int32),
+                ("streams", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -133,7 +134,8 @@ class Plan:
 
     def __init__(self, mol, omega=None, alpha=None, beta=None, schwarz_tol=1e-10, terms=TERMS_ALL,
                  precision=0, device=0, autotune=True, kernel_variant=-1, mixed_tau64=0.1,
-                 mixed_p64=1e4, max_tasks=0, screening=0, deterministic=False, streams=0):
+                 mixed_p64=1e4, max_tasks=0, screening=0, deterministic=False, streams=0,
+                 ml_min_components=0):
         self._keep = [np.ascontiguousarray(mol.coords, dtype=np.float64)]
         for name in ("shell_atom", "shell_l", "shell_nprim", "shell_prim_off", "shell_ao_off"):
             self._keep.append(np.ascontiguousarray(getattr(mol, name), dtype=np.int32))
@@ -145,7 +147,7 @@ class Plan:
         self.params = Params(mol.omega if omega is None else omega, mol.alpha if alpha is None else alpha,
                              mol.beta if beta is None else beta, schwarz_tol, precision, terms,
                              1 if autotune else 0, kernel_variant, mixed_tau64, mixed_p64, max_tasks,
-                             screening, 1 if deterministic else 0, streams)
+                             screening, 1 if deterministic else 0, ml_min_components, streams)
         h = C.c_void_p()
         _check(lib().tdg_plan_create(C.byref(b), C.byref(self.params), device, C.byref(h)))
         self._h = h
