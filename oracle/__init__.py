@@ -65,6 +65,8 @@ def lib():
         L.orc_quartet_bounds.argtypes = [C.POINTER(Basis), vp, vp, vp, i64, vp, vp]
         L.orc_screen_select.argtypes = [C.POINTER(Basis), vp, vp, vp, C.c_double, C.c_int, C.c_int, i64, vp,
                                         vp, C.POINTER(i64)]
+        L.orc_fock_blocks.argtypes = [C.POINTER(Basis), vp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                      C.c_int, i64, vp, vp]
         L.orc_schwarz.argtypes = [C.POINTER(Basis), vp]
         L.orc_eri_tensor.argtypes = [C.POINTER(Basis), C.c_int, C.c_double, vp]
         L.orc_norm_coefs.argtypes = [C.POINTER(Basis), vp]
@@ -72,7 +74,7 @@ def lib():
         L.orc_prim_eri.restype = C.c_double
         L.orc_boys.argtypes = [C.c_int, C.c_double, vp]
         for f in ("orc_grad", "orc_grad_brute", "orc_energy", "orc_quartet_contribs",
-                  "orc_quartet_bounds", "orc_screen_select", "orc_schwarz", "orc_eri_tensor", "orc_norm_coefs"):
+                  "orc_quartet_bounds", "orc_screen_select", "orc_fock_blocks", "orc_schwarz", "orc_eri_tensor", "orc_norm_coefs"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -187,6 +189,36 @@ def screen_select(mol, tau, keep=True, nthreads=0, cap=None, P0=None, PD=None, R
                                    _p(q), _p(bnd), C.byref(n)), "screen_select")
     m = min(n.value, cap)
     return q[:m], bnd[:m]
+
+
+def fock_blocks(mol, B, pairs, cJ=1.0, cK=0.0, cKlr=0.0, omega=None, nthreads=0):
+    """Blocks F[a, b] of the Fock-type matrix for shell pairs [n, 2]; list of arrays."""
+    bb = _Bound(mol)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    nc = (mol.shell_l + 1) * (mol.shell_l + 2) // 2
+    sizes = nc[pr[:, 0]] * nc[pr[:, 1]]
+    out = np.zeros(int(sizes.sum()))
+    _check(lib().orc_fock_blocks(C.byref(bb.b), _p(B), cJ, cK, cKlr, mol.omega if omega is None else omega,
+                                 nthreads, pr.shape[0], _p(pr), _p(out)), "fock_blocks")
+    res, o = [], 0
+    for (a, b_), s in zip(pr, sizes):
+        res.append(out[o:o + s].reshape(nc[a], nc[b_]))
+        o += s
+    return res
+
+
+def fock(mol, B, cJ=1.0, cK=0.0, cKlr=0.0, omega=None, nthreads=0):
+    """The full Fock-type matrix [n_bf, n_bf] (small bases)."""
+    ns = mol.n_shells
+    pairs = np.array([(a, b) for a in range(ns) for b in range(ns)], dtype=np.int32)
+    blocks = fock_blocks(mol, B, pairs, cJ, cK, cKlr, omega, nthreads)
+    F = np.zeros((mol.n_bf, mol.n_bf))
+    nc = (mol.shell_l + 1) * (mol.shell_l + 2) // 2
+    for (a, b), blk in zip(pairs, blocks):
+        oa, ob = mol.shell_ao_off[a], mol.shell_ao_off[b]
+        F[oa:oa + nc[a], ob:ob + nc[b]] = blk
+    return F
 
 
 def schwarz(mol):

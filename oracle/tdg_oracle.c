@@ -34,6 +34,10 @@
  *     the shell-level degeneracy 2^([a!=b]+[c!=d]+[ab!=cd]);
  *   - brute mode: every ordered shell quartet with the literal Gamma.
  *
+ * Also (section II.B, eqs G_2e and zfock): the two-electron part of the
+ * Fock-type matrix of a matrix B, written out by its definition over every
+ * ordered shell quartet (orc_fock_blocks).
+ *
  * Normalisation: every Cartesian component is normalised to one: primitive
  * factor of the x^l component, contraction factor (cross overlaps included)
  * and the angular factor sqrt((2l-1)!!/((2lx-1)!!(2ly-1)!!(2lz-1)!!)).
@@ -916,6 +920,86 @@ int orc_screen_select(const orc_basis_t *b, const double *P0, const double *PD, 
     *n_out = cnt[npair];
     free(cnt); free(pa); free(pb); free(sh);
     screen_free(&scr);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fock-type matrix of section II.B (eq G_2e, eq zfock), two-electron part:  */
+/*   F_mu nu = sum_{lam sig} Bs_{lam sig} [ cJ (mu nu|lam sig)                */
+/*             + cK (mu lam|nu sig) + cKlr (mu lam|nu sig)_lr ],              */
+/* Bs = (B + B^T)/2.  Written out by its definition: the block of F for the   */
+/* shells (a, b) sums over every ordered pair of shells (c, d), with the      */
+/* integral blocks (ab|cd) for the Coulomb term and (ac|bd) for the exchange  */
+/* terms.  out receives, for each requested pair (a, b), its na x nb block    */
+/* (row-major) one after another.                                            */
+int orc_fock_blocks(const orc_basis_t *b, const double *B, double cJ, double cK, double cKlr, double omega,
+                    int nthreads, int64_t npairs, const int32_t *pairs, double *out)
+{
+    init_trip();
+    int rc = check_basis(b);
+    if (rc) return rc;
+    int nth = 1;
+#ifdef _OPENMP
+    nth = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    const int ns = b->n_shells, n = b->n_bf;
+    oshell_t *sh = load_all(b);
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (npairs + 1));
+    off[0] = 0;
+    for (int64_t k = 0; k < npairs; ++k)
+        off[k + 1] = off[k] + (int64_t)ncart(sh[pairs[2 * k]].l) * ncart(sh[pairs[2 * k + 1]].l);
+#pragma omp parallel num_threads(nth)
+    {
+        real *blk = (real *)malloc(sizeof(real) * 1296);
+        real *acc = (real *)malloc(sizeof(real) * 36);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t k = 0; k < npairs; ++k) {
+            const int a = pairs[2 * k], bb = pairs[2 * k + 1];
+            const int na = ncart(sh[a].l), nb = ncart(sh[bb].l);
+            const int oa = b->shell_ao_off[a], ob = b->shell_ao_off[bb];
+            for (int x = 0; x < na * nb; ++x) acc[x] = 0.0;
+            for (int c = 0; c < ns; ++c)
+                for (int d = 0; d < ns; ++d) {
+                    const int nc = ncart(sh[c].l), nd = ncart(sh[d].l);
+                    const int oc = b->shell_ao_off[c], od = b->shell_ao_off[d];
+#define BS(i, j) (0.5L * ((real)B[(size_t)(i) * n + (j)] + (real)B[(size_t)(j) * n + (i)]))
+                    if (cJ != 0.0) { /* (ab|cd) Bs_cd */
+                        const oshell_t *q4[4] = {&sh[a], &sh[bb], &sh[c], &sh[d]};
+                        value_block(q4, 0, 0.0, blk, NULL);
+                        for (int i = 0; i < na; ++i)
+                            for (int j = 0; j < nb; ++j) {
+                                real v = 0.0;
+                                for (int kk = 0; kk < nc; ++kk)
+                                    for (int l = 0; l < nd; ++l)
+                                        v += blk[((i * nb + j) * nc + kk) * nd + l] * BS(oc + kk, od + l);
+                                acc[i * nb + j] += cJ * v;
+                            }
+                    }
+                    for (int op = 0; op < 2; ++op) { /* (a c|b d) Bs_cd: mu in a, lam in c, nu in b, sig in d */
+                        const double cx = op ? cKlr : cK;
+                        if (cx == 0.0) continue;
+                        const oshell_t *q4[4] = {&sh[a], &sh[c], &sh[bb], &sh[d]};
+                        value_block(q4, op, omega, blk, NULL);
+                        for (int i = 0; i < na; ++i)
+                            for (int j = 0; j < nb; ++j) {
+                                real v = 0.0;
+                                for (int kk = 0; kk < nc; ++kk)
+                                    for (int l = 0; l < nd; ++l)
+                                        v += blk[((i * nc + kk) * nb + j) * nd + l] * BS(oc + kk, od + l);
+                                acc[i * nb + j] += cx * v;
+                            }
+                    }
+#undef BS
+                }
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) out[off[k] + i * nb + j] = (double)acc[i * nb + j];
+            (void)oa; (void)ob;
+        }
+        free(blk);
+        free(acc);
+    }
+    free(off);
+    free(sh);
     return 0;
 }
 
