@@ -172,6 +172,8 @@ def main():
     ap.add_argument("--streams", type=int, default=0,
                     help="streams the class kernels of a timed call run on (0 = the library's default, 4); "
                          "profiling runs use 1 so that every kernel is timed alone")
+    ap.add_argument("--no-fock", action="store_true",
+                    help="skip the Fock-type matrix leg (eq G_2e of the chain's relaxed difference density)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy MIB MiB device-to-device (a plain copy of known "
                          "size that calibrates the HBM counters of a profiling run)")
@@ -185,7 +187,7 @@ def main():
     import torch
 
     from paper_2407_16586_amd import synth, tdgrad
-    from paper_2407_16586_amd.workmodel import FLOPS_PER_PRIM
+    from paper_2407_16586_amd.workmodel import FLOPS_PER_PRIM, fock_flops
 
     mol = synth.config1()
     dev = torch.device("cuda:0")
@@ -257,6 +259,49 @@ def main():
                          "all_classes_frac": all_tflops / FP64_VALU_PEAK_TFLOPS},
         }
 
+    def run_fock():
+        """Fock-type matrix of eq G_2e (two-electron part) of the relaxed difference density,
+        FP64, the same screening threshold; timed like the gradient steps."""
+        with open(os.path.join(ROOT, "tests", "golden", "chain60_fock_pd.json")) as fh:
+            gf = json.load(fh)
+        print("bench: Fock-type matrix leg", file=sys.stderr, flush=True)
+        plan = tdgrad.Plan(mol, schwarz_tol=1e-10, precision=0, streams=args.streams)
+        Bd = t(getattr(mol, gf["density"]))
+        F = torch.empty_like(Bd)
+        cf = tuple(gf["coefs"])
+        for _ in range(args.warmup):
+            plan.fock_device(Bd, F, *cf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.fock_device(Bd, F, *cf)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        Fh = F.cpu().numpy()
+        off, sl = mol.shell_ao_off, mol.shell_l
+        nc = (sl + 1) * (sl + 2) // 2
+        err = max(float(np.abs(Fh[off[a]:off[a] + nc[a], off[b]:off[b] + nc[b]] - np.array(blk)).max())
+                  for (a, b), blk in zip(gf["pairs"], gf["blocks"]))
+        st = plan.fock_device(Bd, F, *cf, stats=True)
+        cms = np.array(st["class_ms"])
+        fl = np.array([fock_flops(c, st["class_prim_quartets"][k], st["class_quartets"][k])
+                       for k, c in enumerate(tdgrad.CLASSES)], dtype=np.float64)
+        dom = int(np.argmax(cms))
+        ach = fl[dom] / (cms[dom] * 1e-3) / 1e12
+        plan.close()
+        return {"value": st["quartets"] / (ms * 1e-3), "unit": "quartets/s", "ms_per_call": ms,
+                "quartets": st["quartets"], "prim_quartets": st["prim_quartets"],
+                "kernel_ms_one_stream": float(cms.sum()),
+                "max_abs_err_vs_oracle_blocks": err,
+                "coefs": cf, "density": gf["density"],
+                "roofline": {"bound": "alu", "kernel": f"k_fock{tdgrad.CLASSES[dom]}", "achieved": ach,
+                             "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK_TFLOPS,
+                             "traffic": None, "launch_quartets": int(st["class_quartets"][dom]),
+                             "launch_prim_quartets": int(st["class_prim_quartets"][dom]),
+                             "all_classes_achieved": fl.sum() / (cms.sum() * 1e-3) / 1e12,
+                             "all_classes_frac": fl.sum() / (cms.sum() * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS},
+                "class_ms": {str(c): round(float(m), 4) for c, m in zip(tdgrad.CLASSES, cms)}}
+
     fp64 = run_path(0) if args.path in ("both", "fp64") else None
     mixed = run_path(1) if args.path in ("both", "mixed") else None
     unb = run_path(1, float("inf"), float("inf")) if args.path == "both" and not args.no_unbounded else None
@@ -324,6 +369,8 @@ def main():
             "fp32_fraction": unb["stats"]["fp32_quartets"] / max(1, unb["quartets"]),
             "max_abs_err_vs_oracle": unb["err_oracle"],
             "speedup_vs_fp64": fp64["ms_step"] / unb["ms_step"] if fp64 else None}
+    if not args.no_fock:
+        rec["fock"] = run_fock()
     if args.copy_probe:
         src = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

@@ -294,6 +294,28 @@ int tdg_quartet_contribs(tdg_plan_t *plan, const double *P0, const double *PDelt
                          int32_t ptr_kind, void *hip_stream, int64_t n, const int32_t *quartets,
                          int32_t precision, double *out);
 
+/* Two-electron part of the Fock-type matrix of section II.B (eq G_2e; eq zfock for the
+ * Z-vector and CPHF products), for the plan's basis and geometry:
+ *   F_{mu nu} = sum_{lam sig} Bs_{lam sig} [ cJ (mu nu|lam sig) + cK (mu lam|nu sig)
+ *                                            + cKlr (mu lam|nu sig)_lr ],
+ * Bs = (B + B^T)/2, (|)_lr the erf(omega r)/r integral of eq lreri_k with the plan's omega.
+ * eq G_2e is (cJ, cK, cKlr) = (2, -alpha, -beta) with B = PDelta (symmetric); eq zfock is
+ * (4, -2 alpha, -2 beta), its two exchange orderings summing to twice K(Bs).  The
+ * exchange-correlation kernel term of both equations is not part of this call.
+ * B, F: [n_bf][n_bf] FP64 row-major (F overwritten, symmetric).  ptr_kind 0: host
+ * pointers (synchronous); 1: device pointers on hip_stream (the call waits once on the
+ * stream to read the screening counts).  Screening: a unique shell quartet is skipped when
+ * Q_ab Q_cd times the largest |Bs| element of the six blocks it is contracted with is
+ * below the plan's schwarz_tol (0: no screening); one-centre quartets are kept.  FP64
+ * throughout, whatever the plan's precision.  stats may be NULL; when given, quartets,
+ * prim_quartets, candidates, class_quartets, class_prim_quartets, class_ms (each Fock class
+ * kernel timed alone: the call waits after every launch), chunks, ms_kernels and ms_total
+ * are filled.
+ * Errors: TDG_EINVAL (null pointers, non-finite coefficients, cKlr != 0 with omega <= 0),
+ * TDG_ENOMEM, TDG_EDEVICE. */
+int tdg_fock(tdg_plan_t *plan, const double *B, int32_t ptr_kind, void *hip_stream, double cJ,
+             double cK, double cKlr, double *F, tdg_stats_t *stats);
+
 /* Release a plan and its device memory (NULL is accepted). */
 int tdg_plan_destroy(tdg_plan_t *plan);
 

@@ -12,6 +12,7 @@ TABLE = os.path.join(CSRC, "rys_table.inc")
 GEN = os.path.join(CSRC, "gen_rys_table.py")
 MAIN = os.path.join(CSRC, "tdgrad.hip")
 CLASS_SRC = os.path.join(CSRC, "class_kernels.hip")
+FOCK_SRC = os.path.join(CSRC, "fock_kernels.hip")
 NUM_CLASSES = 21
 
 HIPCC_FLAGS = [
@@ -31,9 +32,11 @@ def table(force: bool = False) -> str:
 # sources each object depends on (for incremental builds)
 _DEV = ["tdg_device.hpp", "rys_table.inc"]
 _DEPS = {
-    "tdgrad": ["tdgrad.hip", "class_launch.hpp", "deriv_kernel.hpp", "mlp.hpp", "../../include/tdgrad.h"] + _DEV,
+    "tdgrad": ["tdgrad.hip", "class_launch.hpp", "deriv_kernel.hpp", "fock_kernel.hpp", "fock_launch.hpp", "mlp.hpp",
+               "../../include/tdgrad.h"] + _DEV,
     "mlp": ["mlp.hip", "mlp.hpp", "../../include/tdgrad.h"],
     "class": ["class_kernels.hip", "class_launch.hpp", "deriv_kernel.hpp", "deriv_wave.hpp"] + _DEV,
+    "fock": ["fock_kernels.hip", "fock_launch.hpp", "fock_kernel.hpp", "deriv_kernel.hpp"] + _DEV,
 }
 
 
@@ -56,6 +59,8 @@ def build(extra_flags: list[str] | None = None, verbose: bool = False, jobs: int
                  (os.path.join(CSRC, "mlp.hip"), os.path.join(odir, "mlp.o"), [], "mlp")]
         for c in range(NUM_CLASSES):
             jobs_.append((CLASS_SRC, os.path.join(odir, f"class_{c}.o"), [f"-DTDG_CLASS={c}"], "class"))
+        for c in range(NUM_CLASSES):
+            jobs_.append((FOCK_SRC, os.path.join(odir, f"fock_{c}.o"), [f"-DTDG_CLASS={c}"], "fock"))
 
         def stale(obj, kind):
             if not incremental or not os.path.exists(obj):

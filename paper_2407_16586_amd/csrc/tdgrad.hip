@@ -29,6 +29,8 @@
 #include "../../include/tdgrad.h"
 #include "class_launch.hpp"
 #include "deriv_kernel.hpp"
+#include "fock_kernel.hpp"
+#include "fock_launch.hpp"
 #include "mlp.hpp"
 
 using namespace tdg;
@@ -202,6 +204,10 @@ struct tdg_plan {
     std::vector<int> b_nprim, b_primoff;
     // deterministic reduction: per-task values and per-block partial gradients
     DevBuf<double> d_tout, d_part;
+    // Fock-type matrix calls: the screening keeps one-centre quartets and has one (FP64) list;
+    // the accumulator G of F = ang (G + G^T) ang
+    int screen_fock = 0;
+    DevBuf<double> d_fockG;
     // host-side state of the current call
     std::vector<int> h_cnt, h_cnt32;
     std::vector<unsigned long long> h_prim, h_cand;
@@ -356,6 +362,42 @@ __global__ void k_density_prep(int n_shells, int n_bf, const int *shell_l, const
     atomicMax(mx, (unsigned long long)__double_as_longlong(m)); // non-negative doubles order as integers
 }
 
+// Fock-type matrix input: one thread per ordered shell pair (a, c); the pair's record holds
+// Bs = (B + B^T)/2 with the angular factors folded in (first slot of the record layout of
+// deriv_kernel.hpp).  The block maxima take the screening bound's P slot (|Bs|) with the D
+// slot at one and R at zero, so that the gradient's bound becomes Q_ab Q_cd times the
+// largest |Bs| of the six blocks a quartet reads; mx receives the square root of the
+// largest |Bs| (its square scales the prefix cut).
+__global__ void k_fock_prep(int n_shells, int n_bf, const int *shell_l, const int *shell_ao, const double *ang,
+                            const double *B, double *dens, BlkMax *bmax, unsigned long long *mx)
+{
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)n_shells * n_shells) return;
+    const int a = (int)(idx / n_shells), c = (int)(idx % n_shells);
+    const int oa = shell_ao[a], oc = shell_ao[c], na = ncart(shell_l[a]), nc = ncart(shell_l[c]);
+    double *rec = dens + dens_rec(n_bf, oa, na, oc);
+    double vb = 0.0;
+    for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nc; ++j) {
+            const double b = 0.5 * (B[(size_t)(oa + i) * n_bf + oc + j] + B[(size_t)(oc + j) * n_bf + oa + i]);
+            rec[i * nc + j] = ang[oa + i] * ang[oc + j] * b;
+            vb = fmax(vb, fabs(b));
+        }
+    BlkMax bm;
+    bm.p = vb; bm.d = 1.0; bm.r = 0.0; bm.pad = 0.0;
+    bmax[idx] = bm;
+    atomicMax(mx, (unsigned long long)__double_as_longlong(sqrt(vb)));
+}
+
+// F = ang (G + G^T) ang, one thread per element
+__global__ void k_fock_finish(int n_bf, const double *ang, const double *G, double *F)
+{
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)n_bf * n_bf) return;
+    const int i = (int)(idx / n_bf), j = (int)(idx % n_bf);
+    F[idx] = ang[i] * ang[j] * (G[idx] + G[(size_t)j * n_bf + i]);
+}
+
 // ======================================================================= screening and task generation
 struct ScreenArgs {
     int cls, pb, pk;
@@ -373,6 +415,8 @@ struct ScreenArgs {
     int *item_cnt32;              // mixed precision: FP32-routed counts / offsets
     const long long *item_off32;
     const double *pair_pmax, *pair_famp;
+    int keep_one_center;          // 1: one-centre quartets are kept (Fock-type matrix; the gradient
+                                  // skips them: their derivative sum vanishes, eq ti)
     int mixed;                    // 1: route to FP32 unless bound >= tau64 or an exponent sum >= p64
     double tau64, p64;
     int2 *tasks;
@@ -448,7 +492,8 @@ __global__ void __launch_bounds__(256) k_screen(ScreenArgs s, const ScreenTable 
     // together.
     auto test = [&](int j, bool valid, bool &keep, bool &to32) {
         const int c = s.pair_sa[j], d = s.pair_sb[j];
-        const bool one_center = (s.shell_atom[c] == ata) && (s.shell_atom[d] == ata) && (atb == ata);
+        const bool one_center = !s.keep_one_center && (s.shell_atom[c] == ata) && (s.shell_atom[d] == ata) &&
+                                (atb == ata);
         const double bnd = Qi * s.pair_Q[j] * block_bound(bm_ab, s.bmax, s.n_shells, a, b, c, d);
         keep = valid && !one_center && (s.tau <= 0.0 || bnd >= s.tau);
         to32 = keep && s.mixed && !hot_i && bnd * famp_i * s.pair_famp[j] < s.tau64 && s.pair_pmax[j] < s.p64;
@@ -803,6 +848,12 @@ static const LaunchFn kLaunch[kNumClasses] = {
     tdg_launch_class_10, tdg_launch_class_11, tdg_launch_class_12, tdg_launch_class_13, tdg_launch_class_14,
     tdg_launch_class_15, tdg_launch_class_16, tdg_launch_class_17, tdg_launch_class_18, tdg_launch_class_19,
     tdg_launch_class_20};
+static const FockFn kFock[kNumClasses] = {
+    tdg_fock_class_0,  tdg_fock_class_1,  tdg_fock_class_2,  tdg_fock_class_3,  tdg_fock_class_4,
+    tdg_fock_class_5,  tdg_fock_class_6,  tdg_fock_class_7,  tdg_fock_class_8,  tdg_fock_class_9,
+    tdg_fock_class_10, tdg_fock_class_11, tdg_fock_class_12, tdg_fock_class_13, tdg_fock_class_14,
+    tdg_fock_class_15, tdg_fock_class_16, tdg_fock_class_17, tdg_fock_class_18, tdg_fock_class_19,
+    tdg_fock_class_20};
 static const ScratchFn kScratch[kNumClasses] = {
     tdg_class_scratch_0,  tdg_class_scratch_1,  tdg_class_scratch_2,  tdg_class_scratch_3,  tdg_class_scratch_4,
     tdg_class_scratch_5,  tdg_class_scratch_6,  tdg_class_scratch_7,  tdg_class_scratch_8,  tdg_class_scratch_9,
@@ -1296,7 +1347,8 @@ static ScreenArgs screen_args(tdg_plan *pl)
     s.shell_atom = pl->d_shell_atom.p; s.pair_Q = pl->d_pair_Q.p;
     s.bmax = pl->d_bmax.p;
     s.n_shells = pl->n_shells; s.tau = pl->prm.schwarz_tol; s.mx = pl->d_mx.p;
-    s.mixed = pl->prm.precision == 1 ? 1 : 0;
+    s.mixed = (pl->prm.precision == 1 && !pl->screen_fock) ? 1 : 0;
+    s.keep_one_center = pl->screen_fock;
     s.tau64 = pl->prm.mixed_tau64; s.p64 = pl->prm.mixed_p64;
     s.pair_pmax = pl->d_pair_pmax.p; s.pair_famp = pl->d_pair_famp.p;
     s.prim_cnt = pl->d_prim_cnt.p; s.cand_cnt = pl->d_cand_cnt.p;
@@ -1357,7 +1409,7 @@ static int count_pass(tdg_plan *pl, hipStream_t st)
     pl->h_prim.assign(kNumClasses, 0);
     pl->h_cand.assign(kNumClasses, 0);
     if (nitems) HIP_TRY(hipMemcpyAsync(pl->h_cnt.data(), pl->d_item_cnt.p, sizeof(int) * nitems, hipMemcpyDeviceToHost, st));
-    if (nitems && pl->prm.precision == 1)
+    if (nitems && s.mixed)
         HIP_TRY(hipMemcpyAsync(pl->h_cnt32.data(), pl->d_item_cnt32.p, sizeof(int) * nitems, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(pl->h_prim.data(), pl->d_prim_cnt.p, 8 * kNumClasses, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(pl->h_cand.data(), pl->d_cand_cnt.p, 8 * kNumClasses, hipMemcpyDeviceToHost, st));
@@ -2487,6 +2539,129 @@ int tdg_quartet_contribs(tdg_plan_t *pl, const double *P0, const double *PD, con
     d_t.release();
     d_o.release();
     return err;
+}
+
+int tdg_fock(tdg_plan_t *pl, const double *B, int32_t ptr_kind, void *hip_stream, double cJ, double cK,
+             double cKlr, double *F, tdg_stats_t *stats)
+{
+    g_err.clear();
+    if (!pl || !B || !F) return fail(TDG_EINVAL, "bad arguments");
+    if (ptr_kind != 0 && ptr_kind != 1) return fail(TDG_EINVAL, "ptr_kind must be 0 or 1");
+    if (!std::isfinite(cJ) || !std::isfinite(cK) || !std::isfinite(cKlr))
+        return fail(TDG_EINVAL, "coefficients must be finite");
+    if (cKlr != 0.0 && !(pl->prm.omega > 0.0)) return fail(TDG_EINVAL, "cKlr != 0 needs a plan with omega > 0");
+    const auto t_start = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipSetDevice(pl->device));
+    const int nbf = pl->n_bf, ns = pl->n_shells;
+    const size_t nn = (size_t)nbf * nbf;
+    int rc;
+    const double *dB = B;
+    if (ptr_kind == 0) {
+        if ((rc = pl->d_in.alloc(3 * nn))) return rc;
+        HIP_TRY(hipMemcpyAsync(pl->d_in.p, B, nn * 8, hipMemcpyHostToDevice, st));
+        dB = pl->d_in.p;
+    }
+    if ((rc = pl->d_fockG.alloc(nn))) return rc;
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (double *)pl->d_mx.p, 1);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (double *)pl->d_prim_cnt.p, (long long)kNumClasses);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (double *)pl->d_cand_cnt.p, (long long)kNumClasses);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, pl->d_fockG.p, (long long)nn);
+    const long long nblk = (long long)ns * ns;
+    hipLaunchKernelGGL(k_fock_prep, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, ns, nbf, pl->d_shell_l.p,
+                       pl->d_shell_ao.p, pl->d_ang.p, dB, pl->d_dens.p, pl->d_bmax.p, pl->d_mx.p);
+    HIP_TRY(hipGetLastError());
+    // the screening passes of this call keep one-centre quartets and route nothing to FP32
+    struct FockScreen {
+        tdg_plan *p;
+        ~FockScreen() { p->screen_fock = 0; }
+    } guard{pl};
+    pl->screen_fock = 1;
+    if ((rc = count_pass(pl, st))) return rc;
+    HIP_TRY(hipStreamSynchronize(st));
+    if (!pl->ncu) {
+        hipDeviceProp_t prop;
+        pl->ncu = hipGetDeviceProperties(&prop, pl->device) == hipSuccess ? prop.multiProcessorCount : 256;
+    }
+    FockArgs fa{};
+    fa.coords = pl->d_coords.p; fa.shell_atom = pl->d_shell_atom.p; fa.shell_ao = pl->d_shell_ao.p;
+    fa.pair_sa = pl->d_pair_sa.p; fa.pair_sb = pl->d_pair_sb.p; fa.pair_ppoff = pl->d_pair_ppoff.p;
+    fa.pair_npp = pl->d_pair_npp.p;
+    fa.pp_rec = reinterpret_cast<const double2 *>(pl->d_pp_rec.p);
+    fa.bmat = pl->d_dens.p; fa.n_bf = nbf;
+    fa.omega = pl->prm.omega; fa.cJ = cJ; fa.cK = cK; fa.cKlr = cKlr;
+    fa.G = pl->d_fockG.p;
+    const bool lr = cKlr != 0.0;
+    const int nitems = pl->item_class_off[kNumClasses];
+    long long cls_q[kNumClasses] = {0};
+    long long total = 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+        if (!class_active(pl, c)) continue;
+        for (int k = pl->item_class_off[c]; k < pl->item_class_off[c + 1]; ++k) cls_q[c] += pl->h_cnt[k];
+        total += cls_q[c];
+    }
+    // the task list is built in chunks of bra pairs holding at most 2^27 quartets; the kernels
+    // of a chunk run before the next chunk's fill pass rewrites the list (same stream)
+    constexpr long long kFockChunk = 1LL << 27;
+    long long nchunks = 0;
+    double kms = 0.0, cls_ms[kNumClasses] = {0.0};
+    int K0 = 0;
+    while (K0 < nitems) {
+        int K1 = K0;
+        long long acc = 0;
+        for (int c = 0; K1 < nitems; ++K1) {
+            while (K1 >= pl->item_class_off[c + 1]) ++c;
+            const long long v = class_active(pl, c) ? (long long)pl->h_cnt[K1] : 0;
+            if (acc + v > kFockChunk && K1 > K0) break;
+            acc += v;
+        }
+        Chunk ch;
+        if ((rc = fill_items(pl, st, K0, K1, ch))) return rc;
+        ++nchunks;
+        for (int c = 0; c < kNumClasses; ++c) {
+            const long long b = ch.seg_begin[c][0], e = ch.seg_end[c][0];
+            if (e <= b) continue;
+            fa.tasks = pl->d_tasks.p + b;
+            fa.ntasks = e - b;
+            if (stats) HIP_TRY(hipEventRecord(pl->ev0, st));
+            if (kFock[c](fa, lr, st, pl->ncu * kGridPerCU) != hipSuccess)
+                return fail(TDG_EDEVICE, "Fock class %d launch failed", c);
+            if (stats) { // each class kernel timed alone (HIP events on the call's stream)
+                HIP_TRY(hipEventRecord(pl->ev1, st));
+                HIP_TRY(hipEventSynchronize(pl->ev1));
+                float ms = 0.0f;
+                HIP_TRY(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
+                cls_ms[c] += ms;
+                kms += ms;
+            }
+        }
+        K0 = K1;
+    }
+    double *dF = F;
+    if (ptr_kind == 0) dF = pl->d_in.p + nn; // staging slot behind the copy of B
+    hipLaunchKernelGGL(k_fock_finish, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, nbf, pl->d_ang.p,
+                       pl->d_fockG.p, dF);
+    HIP_TRY(hipGetLastError());
+    if (ptr_kind == 0) {
+        HIP_TRY(hipMemcpyAsync(F, dF, nn * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (stats) {
+        HIP_TRY(hipStreamSynchronize(st));
+        std::memset(stats, 0, sizeof(*stats));
+        stats->quartets = total;
+        for (int c = 0; c < kNumClasses; ++c) {
+            stats->class_quartets[c] = cls_q[c];
+            stats->class_ms[c] = cls_ms[c];
+            stats->class_prim_quartets[c] = (int64_t)pl->h_prim[c];
+            stats->prim_quartets += (int64_t)pl->h_prim[c];
+            stats->candidates += (int64_t)pl->h_cand[c];
+        }
+        stats->chunks = nchunks;
+        stats->ms_kernels = kms;
+        stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return TDG_OK;
 }
 
 } // extern "C"

@@ -24,6 +24,7 @@ CLASSES = tuple(PAIR_CLASSES[b] + PAIR_CLASSES[k] for b in range(6) for k in ran
 EXPORTED = ("tdg_plan_create", "tdg_grad_jk", "tdg_grad_jk_batch", "tdg_plan_destroy", "tdg_plan_dims",
             "tdg_plan_schwarz", "tdg_rys_rule", "tdg_plan_set_screen_model", "tdg_collect",
             "tdg_plan_update_coords", "tdg_screen_list", "tdg_quartet_contribs", "tdg_grad_jk_noalloc", "tdg_plan_set_streams",
+            "tdg_fock",
             "tdg_mlp_create", "tdg_mlp_destroy", "tdg_mlp_nweights", "tdg_mlp_set_weights",
             "tdg_mlp_get_weights", "tdg_mlp_forward", "tdg_mlp_grad", "tdg_mlp_train_step",
             "tdg_last_error")
@@ -105,6 +106,8 @@ def lib():
         L.tdg_screen_list.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, C.c_int64, C.c_int64,
                                       C.POINTER(C.c_int64)]
         L.tdg_quartet_contribs.argtypes = [vp, vp, vp, vp, C.c_int32, vp, C.c_int64, vp, C.c_int32, vp]
+        L.tdg_fock.argtypes = [vp, vp, C.c_int32, vp, C.c_double, C.c_double, C.c_double, vp,
+                               C.POINTER(Stats)]
         L.tdg_mlp_create.argtypes = [C.c_int, C.c_uint64, C.POINTER(vp)]
         L.tdg_mlp_destroy.argtypes = [vp]
         L.tdg_mlp_nweights.argtypes = []
@@ -220,6 +223,32 @@ class Plan:
         _check(lib().tdg_quartet_contribs(self._h, _ptr(P0), _ptr(PD), _ptr(R), 0, None, q.shape[0],
                                           _ptr(q), precision, _ptr(out)))
         return out
+
+    def fock(self, B, cJ=1.0, cK=0.0, cKlr=0.0, stats=False):
+        """Host numpy B [n_bf, n_bf] -> host Fock-type matrix (synchronous); see tdg_fock."""
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        n = self.n_bf
+        if B.shape != (n, n):
+            raise ValueError(f"B must be {n}x{n}, got {B.shape}")
+        out = np.zeros((n, n))
+        st = Stats()
+        _check(lib().tdg_fock(self._h, _ptr(B), 0, None, float(cJ), float(cK), float(cKlr), _ptr(out),
+                              C.byref(st) if stats else None))
+        return (out, st.as_dict()) if stats else out
+
+    def fock_device(self, B, out, cJ=1.0, cK=0.0, cKlr=0.0, stream=None, stats=False):
+        """torch float64 device tensors B and out [n_bf, n_bf]; queued on `stream` (default:
+        torch's current stream), with one wait on it for the screening counts."""
+        import torch
+        n = self.n_bf
+        for x in (B, out):
+            if x.dtype != torch.float64 or not x.is_contiguous() or tuple(x.shape) != (n, n) or not x.is_cuda:
+                raise ValueError("B and out must be contiguous float64 device tensors of shape (n_bf, n_bf)")
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        st = Stats()
+        _check(lib().tdg_fock(self._h, B.data_ptr(), 1, s, float(cJ), float(cK), float(cKlr), out.data_ptr(),
+                              C.byref(st) if stats else None))
+        return st.as_dict() if stats else None
 
     def set_screen_model(self, model, log10_threshold=-12.0, tau_hi=1e-6):
         """Attach a trained Estimator (or None); it vetoes quartets after the Schwarz

@@ -52,3 +52,30 @@ def flops_per_prim_quartet(cls, long_range: bool = True) -> int:
 
 
 FLOPS_PER_PRIM = {c: flops_per_prim_quartet(c) for c in CLASSES}
+
+
+# ---------------------------------------------------------------------------
+# Fock-type matrix (section II.B, eqs G_2e and zfock), per primitive quartet of a class,
+# with n = floor(L/2) + 1 roots per kernel (no derivative) and, per root,
+#   roots     : 52 flop (as above)
+#   VRR/HRR   : the same recurrences for momenta (la+lb, lc+ld) per direction
+#   contract  : N components, two products and one sum of the three 2D factors = 3 flop
+# and per shell quartet (once, after the primitive sums): the six output blocks J_ab, J_cd,
+# K_ac, K_ad, K_bc, K_bd, N multiply-adds each = 12 N flop, plus 3 N flop that weight and
+# combine the full- and long-range exchange integrals.
+def fock_flops_per_root(la, lb, lc, ld) -> int:
+    nm, mm = la + lb, lc + ld
+    vrr = 5 * (nm + 1) * (mm + 1)
+    hrr_bra = sum((nm - j) * (mm + 1) for j in range(lb + 1))
+    hrr_ket = sum((la + 1) * (lb + 1) * (mm - l) for l in range(ld + 1))
+    per_dir = vrr + 2 * (hrr_bra + hrr_ket)
+    n = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
+    return 52 + 3 * per_dir + 3 * n
+
+
+def fock_flops(cls, prim_quartets: int, quartets: int, long_range: bool = True) -> int:
+    la, lb, lc, ld = cls
+    sets = 2 if long_range else 1
+    n = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
+    per_prim = 30 + sets * ((la + lb + lc + ld) // 2 + 1) * fock_flops_per_root(la, lb, lc, ld)
+    return per_prim * prim_quartets + 15 * n * quartets

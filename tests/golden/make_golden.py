@@ -1,5 +1,6 @@
-"""Write the oracle's gradients for the stored parity cases (calls only oracle/ and the
-seeded input generator).  Usage: python tests/golden/make_golden.py [name ...]"""
+"""Write the oracle's gradients (and sampled Fock-type matrix blocks) for the stored parity
+cases (calls only oracle/ and the seeded input generator).
+Usage: python tests/golden/make_golden.py [name ...]"""
 import json
 import os
 import sys
@@ -24,8 +25,38 @@ CASES = {
     "droplet61_tau1e-10": dict(mol=lambda: synth.config2_molecule(32), tau=1e-10),
 }
 
+FOCK_CASES = {
+    # Fock-type matrix of eq G_2e, (cJ, cK, cKlr) = (2, -alpha, -beta), of the chain's relaxed
+    # difference density: blocks of 10 shell pairs (seeded sample, diagonal pair included)
+    "chain60_fock_pd": dict(mol=synth.config1, dens="PD", npairs=10, seed=21),
+}
+
+
+def make_fock(name):
+    spec = FOCK_CASES[name]
+    mol = spec["mol"]()
+    B = getattr(mol, spec["dens"])
+    rng = np.random.default_rng(spec["seed"])
+    ns = mol.n_shells
+    sl = np.asarray(mol.shell_l)
+    pick = lambda l: int(rng.choice(np.where(sl == l)[0]))
+    pairs = [(0, 0)] + [(pick(la), pick(lb)) for la, lb in ((1, 1), (2, 0), (2, 1), (2, 2))]
+    pairs += [tuple(int(x) for x in rng.integers(0, ns, 2)) for _ in range(spec["npairs"] - len(pairs))]
+    cf = (2.0, -mol.alpha, -mol.beta)
+    t = time.time()
+    blocks = oracle.fock_blocks(mol, B, np.array(pairs, dtype=np.int32), *cf)
+    dt = time.time() - t
+    out = {"case": name, "density": spec["dens"], "coefs": cf, "n_bf": mol.n_bf, "pairs": pairs,
+           "blocks": [b.tolist() for b in blocks], "oracle_seconds": dt,
+           "generator": "tests/golden/make_golden.py (oracle.fock_blocks, synthetic seeded inputs)"}
+    with open(os.path.join(HERE, name + ".json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(name, f"{dt:.1f}s", flush=True)
+
 
 def make(name):
+    if name in FOCK_CASES:
+        return make_fock(name)
     spec = CASES[name]
     mol = spec["mol"]()
     t = time.time()
@@ -41,5 +72,5 @@ def make(name):
 
 if __name__ == "__main__":
     oracle.build(force=False)
-    for n in (sys.argv[1:] or CASES):
+    for n in (sys.argv[1:] or list(CASES) + list(FOCK_CASES)):
         make(n)
