@@ -58,6 +58,9 @@ struct FockClass {
     static constexpr int OB_CD = 0, OB_AB = NC * ND, OB_BD = OB_AB + NA * NB, OB_BC = OB_BD + NB * ND,
                          OB_AD = OB_BC + NB * NC, OB_AC = OB_AD + NA * ND, SB = OB_AC + NA * NC;
     static constexpr int GSTRIDE = UN + SB + 1;
+    // Rys table of the class in LDS when it fits beside the groups (n <= 3 roots)
+    static constexpr bool TAB_LDS = NR <= 3;
+    static constexpr int TAB_N = TAB_LDS ? rys_table_size<NR>() : 1;
     static constexpr int WAVES = 2;
     static constexpr int QPB = QPW * WAVES;
     static constexpr int BLOCK = WAVES * kWave;
@@ -71,6 +74,11 @@ __global__ void __launch_bounds__((FockClass<LA, LB, LC, LD, LR>::BLOCK)) k_fock
     constexpr int NR = K::NR, G = K::G, QPW = K::QPW, QPB = K::QPB, CPL = K::CPL;
     constexpr int NA = K::NA, NB = K::NB, NC = K::NC, ND = K::ND, N = K::N, NBASE = K::NBASE;
     __shared__ double s_buf[QPB * K::GSTRIDE];
+    __shared__ double s_rys[K::TAB_N];
+    if constexpr (K::TAB_LDS) {
+        rys_table_to_lds<NR>(s_rys);
+        __syncthreads();
+    }
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int grp = lane / G, t = lane % G;
@@ -126,9 +134,13 @@ __global__ void __launch_bounds__((FockClass<LA, LB, LC, LD, LR>::BLOCK)) k_fock
                 const double p = b0.x, ip = b0.y;
                 const double cab = 34.98683665524972 * b1.x * ip; // 2 pi^(5/2) c_ab / p
                 const double P[3] = {b2.y, b3.x, b3.y};
+                // next ket record requested one primitive ahead
+                double2 n0 = rk[0], n1 = rk[1], n2 = rk[2], n3 = rk[3];
                 for (int ik = 0; ik < nkp; ++ik) {
+                    const double2 k0 = n0, k1 = n1, k2 = n2, k3 = n3;
+                    const int kn = ik + 1 < nkp ? ik + 1 : ik;
+                    n0 = rk[4 * kn]; n1 = rk[4 * kn + 1]; n2 = rk[4 * kn + 2]; n3 = rk[4 * kn + 3];
                     if (job) {
-                        const double2 k0 = rk[4 * ik], k1 = rk[4 * ik + 1], k2 = rk[4 * ik + 2], k3 = rk[4 * ik + 3];
                         const double qq = k0.x, iq = k0.y, ccd = k1.x;
                         const double Q[3] = {k2.y, k3.x, k3.y};
                         const double sipq = rsq64(p + qq), ipq = sipq * sipq;
@@ -143,7 +155,8 @@ __global__ void __launch_bounds__((FockClass<LA, LB, LC, LD, LR>::BLOCK)) k_fock
                             Tr *= eta;
                         }
                         double u, w;
-                        rys_root<NR>(Tr, jroot, u, w);
+                        if constexpr (K::TAB_LDS) rys_root_lds<NR>(s_rys, Tr, jroot, u, w);
+                        else rys_root<NR>(Tr, jroot, u, w);
                         if (LR && jset) {
                             u *= eta;
                             w *= seta;
@@ -257,6 +270,232 @@ __global__ void __launch_bounds__((FockClass<LA, LB, LC, LD, LR>::BLOCK)) k_fock
 #undef V_
         }
         wave_sync(); // the next quartet's tables overwrite this one's integrals
+    }
+}
+
+// Lane layout for the classes with few components (N <= 27): one lane per shell quartet
+// evaluates every root of both kernels with its base tables in registers, keeps the N
+// contracted integrals of each kernel in registers, and forms the six output blocks
+// itself (compile-time indices throughout); the Rys table of the class sits in LDS.  No
+// wavefront synchronisation inside the task loop.
+template <int LA, int LB, int LC, int LD, bool LR>
+struct FockLane {
+    static constexpr int L = LA + LB + LC + LD;
+    static constexpr int NR = L / 2 + 1;
+    static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    static constexpr int N = NA * NB * NC * ND;
+    static constexpr int NBASE = (LA + 1) * (LB + 1) * (LC + 1) * (LD + 1);
+    static constexpr bool TAB_LDS = NR <= 3;
+    static constexpr int TAB_N = TAB_LDS ? rys_table_size<NR>() : 1;
+    static constexpr int BLOCK = 128;
+};
+
+template <int LA, int LB, int LC, int LD>
+__device__ __forceinline__ constexpr int fock_e(int c, int d)
+{
+    constexpr int NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    const int id = c % ND, ic = (c / ND) % NC, ib = (c / (ND * NC)) % NB, ia = c / (ND * NC * NB);
+    return ((kCart.v[LA][ia][d] * (LB + 1) + kCart.v[LB][ib][d]) * (LC + 1) + kCart.v[LC][ic][d]) * (LD + 1) +
+           kCart.v[LD][id][d];
+}
+
+template <int LA, int LB, int LC, int LD, bool LR>
+__global__ void __launch_bounds__(128) k_fock_lane(const FockArgs a)
+{
+    using K = FockLane<LA, LB, LC, LD, LR>;
+    constexpr int NR = K::NR, N = K::N, NBASE = K::NBASE;
+    constexpr int NA = K::NA, NB = K::NB, NC = K::NC, ND = K::ND;
+    __shared__ double s_rys[K::TAB_N];
+    if constexpr (K::TAB_LDS) {
+        rys_table_to_lds<NR>(s_rys);
+        __syncthreads();
+    }
+    const double iom2 = LR ? 1.0 / (a.omega * a.omega) : 0.0;
+    const bool doJ = a.cJ != 0.0, doK = a.cK != 0.0 || (LR && a.cKlr != 0.0);
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    // every lane of a block takes the same number of rounds (the J_ab reduction below is a
+    // wavefront operation); lanes past the end carry no task
+    for (long long t0 = (long long)blockIdx.x * blockDim.x; t0 < a.ntasks; t0 += stride) {
+        const long long ti = t0 + threadIdx.x;
+        const bool valid = ti < a.ntasks;
+        const int2 tk = a.tasks[valid ? ti : a.ntasks - 1];
+        const int bra = tk.x, ket = tk.y;
+        const int sa = a.pair_sa[bra], sb = a.pair_sb[bra], sc = a.pair_sa[ket], sd = a.pair_sb[ket];
+        const int atA = a.shell_atom[sa], atB = a.shell_atom[sb], atC = a.shell_atom[sc], atD = a.shell_atom[sd];
+        double A[3], AB[3], Cc[3], CD[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            A[d] = a.coords[3 * atA + d];
+            AB[d] = A[d] - a.coords[3 * atB + d];
+            Cc[d] = a.coords[3 * atC + d];
+            CD[d] = Cc[d] - a.coords[3 * atD + d];
+        }
+        double v0[N], v1[LR ? N : 1];
+#pragma unroll
+        for (int c = 0; c < N; ++c) v0[c] = 0.0;
+#pragma unroll
+        for (int c = 0; c < (LR ? N : 1); ++c) v1[c] = 0.0;
+        const int pb0 = a.pair_ppoff[bra], nbp = valid ? a.pair_npp[bra] : 0;
+        const int pk0 = a.pair_ppoff[ket], nkp = a.pair_npp[ket];
+        const double2 *rb = a.pp_rec + 4 * (size_t)pb0, *rk = a.pp_rec + 4 * (size_t)pk0;
+        for (int ib = 0; ib < nbp; ++ib) {
+            const double2 b0 = rb[4 * ib], b1 = rb[4 * ib + 1], b2 = rb[4 * ib + 2], b3 = rb[4 * ib + 3];
+            const double p = b0.x, ip = b0.y;
+            const double cab = 34.98683665524972 * b1.x * ip; // 2 pi^(5/2) c_ab / p
+            const double P[3] = {b2.y, b3.x, b3.y};
+            // ket record of the current primitive; the next one is requested before the
+            // current one's work so that its latency is hidden behind it
+            double2 n0 = rk[0], n1 = rk[1], n2 = rk[2], n3 = rk[3];
+            for (int ik = 0; ik < nkp; ++ik) {
+                const double2 k0 = n0, k1 = n1, k2 = n2, k3 = n3;
+                const int kn = ik + 1 < nkp ? ik + 1 : ik;
+                n0 = rk[4 * kn]; n1 = rk[4 * kn + 1]; n2 = rk[4 * kn + 2]; n3 = rk[4 * kn + 3];
+                const double qq = k0.x, iq = k0.y, ccd = k1.x;
+                const double Q[3] = {k2.y, k3.x, k3.y};
+                const double sipq = rsq64(p + qq), ipq = sipq * sipq;
+                const double rho = p * qq * ipq;
+                double PQ[3], pq2 = 0.0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    PQ[d] = P[d] - Q[d];
+                    pq2 += PQ[d] * PQ[d];
+                }
+                const double base_pref = cab * (ccd * iq) * sipq;
+#pragma unroll
+                for (int set = 0; set < (LR ? 2 : 1); ++set) {
+                    double Tr = rho * pq2, eta = 1.0, seta = 1.0;
+                    if (set) {
+                        seta = rsq64(1.0 + rho * iom2); // sqrt(omega^2 / (omega^2 + rho))
+                        eta = seta * seta;
+                        Tr *= eta;
+                    }
+#pragma unroll 1
+                    for (int r = 0; r < NR; ++r) {
+                        double u, w;
+                        if constexpr (K::TAB_LDS) rys_root_lds<NR>(s_rys, Tr, r, u, w);
+                        else rys_root<NR>(Tr, r, u, w);
+                        if (set) {
+                            u *= eta;
+                            w *= seta;
+                        }
+                        const double B00 = 0.5 * u * ipq;
+                        const double B10 = 0.5 * ip * (1.0 - qq * ipq * u);
+                        const double B01 = 0.5 * iq * (1.0 - p * ipq * u);
+                        const double cq = qq * ipq * u, cp = p * ipq * u;
+                        double I[3][NBASE];
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const double CA = (P[d] - A[d]) - cq * PQ[d], CB = CA + AB[d];
+                            const double CCx = (Q[d] - Cc[d]) + cp * PQ[d], CDx = CCx + CD[d];
+                            direct_base<LA, LB, LC, LD, double>(I[d], d == 2 ? base_pref * w : 1.0, CA, CB, CCx, CDx,
+                                                                B10, B01, B00);
+                        }
+#pragma unroll
+                        for (int c = 0; c < N; ++c) {
+                            const double v = I[0][fock_e<LA, LB, LC, LD>(c, 0)] * I[1][fock_e<LA, LB, LC, LD>(c, 1)] *
+                                             I[2][fock_e<LA, LB, LC, LD>(c, 2)];
+                            if (set) v1[LR ? c : 0] += v;
+                            else v0[c] += v;
+                        }
+                    }
+                }
+            }
+        }
+        const double deg = (sa != sb ? 2.0 : 1.0) * (sc != sd ? 2.0 : 1.0) * (bra != ket ? 2.0 : 1.0);
+        const double wJ = 0.25 * deg * a.cJ, wK = 0.125 * deg;
+        double vK[N];
+#pragma unroll
+        for (int c = 0; c < N; ++c) vK[c] = wK * (a.cK * v0[c] + (LR ? a.cKlr * v1[LR ? c : 0] : 0.0));
+        const int n = a.n_bf;
+        const int oa = a.shell_ao[sa], ob = a.shell_ao[sb], oc = a.shell_ao[sc], od = a.shell_ao[sd];
+        const double *Bcd = a.bmat + dens_rec(n, oc, NC, od), *Bab = a.bmat + dens_rec(n, oa, NA, ob);
+        const double *Bbd = a.bmat + dens_rec(n, ob, NB, od), *Bbc = a.bmat + dens_rec(n, ob, NB, oc);
+        const double *Bad = a.bmat + dens_rec(n, oa, NA, od), *Bac = a.bmat + dens_rec(n, oa, NA, oc);
+#define V_(i, j, k, l) ((((i) * NB + (j)) * NC + (k)) * ND + (l))
+        if (doJ) {
+            // J_ab: the tasks of a class segment are ordered by bra pair, so the lanes of a
+            // wavefront mostly share it; then the wavefront sums each element first and one
+            // lane adds it (instead of 64 atomic adds to one address)
+            const int bra0 = __shfl(bra, 0);
+            const bool same_bra = __all(!valid || bra == bra0);
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int k = 0; k < NC; ++k)
+#pragma unroll
+                        for (int l = 0; l < ND; ++l) s += v0[V_(i, j, k, l)] * Bcd[k * ND + l];
+                    s = valid ? wJ * s : 0.0;
+                    if (same_bra) {
+#pragma unroll
+                        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+                        if ((threadIdx.x & (kWave - 1)) == 0 && s != 0.0)
+                            atomic_add_global(a.G + (size_t)(oa + i) * n + ob + j, s);
+                    } else if (s != 0.0) {
+                        atomic_add_global(a.G + (size_t)(oa + i) * n + ob + j, s);
+                    }
+                }
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+#pragma unroll
+                for (int l = 0; l < ND; ++l) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int i = 0; i < NA; ++i)
+#pragma unroll
+                        for (int j = 0; j < NB; ++j) s += v0[V_(i, j, k, l)] * Bab[i * NB + j];
+                    if (valid && s != 0.0) atomic_add_global(a.G + (size_t)(oc + k) * n + od + l, wJ * s);
+                }
+        }
+        if (doK && valid) {
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) { // K_ac
+                    double s = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j)
+#pragma unroll
+                        for (int l = 0; l < ND; ++l) s += vK[V_(i, j, k, l)] * Bbd[j * ND + l];
+                    if (s != 0.0) atomic_add_global(a.G + (size_t)(oa + i) * n + oc + k, s);
+                }
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int l = 0; l < ND; ++l) { // K_ad
+                    double s = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j)
+#pragma unroll
+                        for (int k = 0; k < NC; ++k) s += vK[V_(i, j, k, l)] * Bbc[j * NC + k];
+                    if (s != 0.0) atomic_add_global(a.G + (size_t)(oa + i) * n + od + l, s);
+                }
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) { // K_bc
+                    double s = 0.0;
+#pragma unroll
+                    for (int i = 0; i < NA; ++i)
+#pragma unroll
+                        for (int l = 0; l < ND; ++l) s += vK[V_(i, j, k, l)] * Bad[i * ND + l];
+                    if (s != 0.0) atomic_add_global(a.G + (size_t)(ob + j) * n + oc + k, s);
+                }
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int l = 0; l < ND; ++l) { // K_bd
+                    double s = 0.0;
+#pragma unroll
+                    for (int i = 0; i < NA; ++i)
+#pragma unroll
+                        for (int k = 0; k < NC; ++k) s += vK[V_(i, j, k, l)] * Bac[i * NC + k];
+                    if (s != 0.0) atomic_add_global(a.G + (size_t)(ob + j) * n + od + l, s);
+                }
+        }
+#undef V_
     }
 }
 
