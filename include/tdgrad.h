@@ -306,15 +306,20 @@ int tdg_quartet_contribs(tdg_plan_t *plan, const double *P0, const double *PDelt
  * pointers (synchronous); 1: device pointers on hip_stream (the call waits once on the
  * stream to read the screening counts).  Screening: a unique shell quartet is skipped when
  * Q_ab Q_cd times the largest |Bs| element of the six blocks it is contracted with is
- * below the plan's schwarz_tol (0: no screening); one-centre quartets are kept.  FP64
+ * below the plan's schwarz_tol (0: no screening); one-centre quartets are kept.
+ * relative = 1 screens as if B were first scaled to a largest |Bs| element of one and F
+ * scaled back (the threshold becomes schwarz_tol max|Bs|): the normalisation of the
+ * Krylov vectors before the Fock build discussed in section III.B, which keeps the shrinking
+ * vectors of late Z-vector iterations from being screened away; 0 = absolute.  FP64
  * throughout, whatever the plan's precision.  stats may be NULL; when given, quartets,
  * prim_quartets, candidates, class_quartets, class_prim_quartets, class_ms (each Fock class
  * kernel timed alone: the call waits after every launch), chunks, ms_kernels and ms_total
  * are filled.
- * Errors: TDG_EINVAL (null pointers, non-finite coefficients, cKlr != 0 with omega <= 0),
+ * Errors: TDG_EINVAL (null pointers, non-finite coefficients, cKlr != 0 with omega <= 0,
+ * relative not 0 or 1),
  * TDG_ENOMEM, TDG_EDEVICE. */
 int tdg_fock(tdg_plan_t *plan, const double *B, int32_t ptr_kind, void *hip_stream, double cJ,
-             double cK, double cKlr, double *F, tdg_stats_t *stats);
+             double cK, double cKlr, int32_t relative, double *F, tdg_stats_t *stats);
 
 /* Release a plan and its device memory (NULL is accepted). */
 int tdg_plan_destroy(tdg_plan_t *plan);

@@ -415,6 +415,8 @@ struct ScreenArgs {
     int *item_cnt32;              // mixed precision: FP32-routed counts / offsets
     const long long *item_off32;
     const double *pair_pmax, *pair_famp;
+    int tau_rel;                  // 1: the threshold is tau times the largest density factor (the
+                                  // screening of a matrix scaled to unit largest element)
     int keep_one_center;          // 1: one-centre quartets are kept (Fock-type matrix; the gradient
                                   // skips them: their derivative sum vanishes, eq ti)
     int mixed;                    // 1: route to FP32 unless bound >= tau64 or an exponent sum >= p64
@@ -481,7 +483,8 @@ __global__ void __launch_bounds__(256) k_screen(ScreenArgs s, const ScreenTable 
     const int a = s.pair_sa[i], b = s.pair_sb[i];
     const double Qi = s.pair_Q[i];
     const double mxv = __longlong_as_double((long long)*s.mx);
-    const double cut = s.tau > 0.0 ? s.tau / (Qi * mxv * mxv) : -1.0;
+    const double tau = s.tau_rel ? s.tau * mxv * mxv : s.tau;
+    const double cut = tau > 0.0 ? tau / (Qi * mxv * mxv) : -1.0;
     const int ata = s.shell_atom[a], atb = s.shell_atom[b];
     const BlkMax bm_ab = s.bmax[(size_t)a * s.n_shells + b];
     const int Ki = s.pair_K[i];
@@ -495,7 +498,7 @@ __global__ void __launch_bounds__(256) k_screen(ScreenArgs s, const ScreenTable 
         const bool one_center = !s.keep_one_center && (s.shell_atom[c] == ata) && (s.shell_atom[d] == ata) &&
                                 (atb == ata);
         const double bnd = Qi * s.pair_Q[j] * block_bound(bm_ab, s.bmax, s.n_shells, a, b, c, d);
-        keep = valid && !one_center && (s.tau <= 0.0 || bnd >= s.tau);
+        keep = valid && !one_center && (tau <= 0.0 || bnd >= tau);
         to32 = keep && s.mixed && !hot_i && bnd * famp_i * s.pair_famp[j] < s.tau64 && s.pair_pmax[j] < s.p64;
     };
     // end of the Q-sorted prefix of group g that can pass the bound: the first ket with
@@ -1348,7 +1351,8 @@ static ScreenArgs screen_args(tdg_plan *pl)
     s.bmax = pl->d_bmax.p;
     s.n_shells = pl->n_shells; s.tau = pl->prm.schwarz_tol; s.mx = pl->d_mx.p;
     s.mixed = (pl->prm.precision == 1 && !pl->screen_fock) ? 1 : 0;
-    s.keep_one_center = pl->screen_fock;
+    s.keep_one_center = pl->screen_fock ? 1 : 0;
+    s.tau_rel = pl->screen_fock == 2 ? 1 : 0;
     s.tau64 = pl->prm.mixed_tau64; s.p64 = pl->prm.mixed_p64;
     s.pair_pmax = pl->d_pair_pmax.p; s.pair_famp = pl->d_pair_famp.p;
     s.prim_cnt = pl->d_prim_cnt.p; s.cand_cnt = pl->d_cand_cnt.p;
@@ -2542,7 +2546,7 @@ int tdg_quartet_contribs(tdg_plan_t *pl, const double *P0, const double *PD, con
 }
 
 int tdg_fock(tdg_plan_t *pl, const double *B, int32_t ptr_kind, void *hip_stream, double cJ, double cK,
-             double cKlr, double *F, tdg_stats_t *stats)
+             double cKlr, int32_t relative, double *F, tdg_stats_t *stats)
 {
     g_err.clear();
     if (!pl || !B || !F) return fail(TDG_EINVAL, "bad arguments");
@@ -2550,6 +2554,7 @@ int tdg_fock(tdg_plan_t *pl, const double *B, int32_t ptr_kind, void *hip_stream
     if (!std::isfinite(cJ) || !std::isfinite(cK) || !std::isfinite(cKlr))
         return fail(TDG_EINVAL, "coefficients must be finite");
     if (cKlr != 0.0 && !(pl->prm.omega > 0.0)) return fail(TDG_EINVAL, "cKlr != 0 needs a plan with omega > 0");
+    if (relative != 0 && relative != 1) return fail(TDG_EINVAL, "relative must be 0 or 1");
     const auto t_start = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)hip_stream;
     HIP_TRY(hipSetDevice(pl->device));
@@ -2576,7 +2581,7 @@ int tdg_fock(tdg_plan_t *pl, const double *B, int32_t ptr_kind, void *hip_stream
         tdg_plan *p;
         ~FockScreen() { p->screen_fock = 0; }
     } guard{pl};
-    pl->screen_fock = 1;
+    pl->screen_fock = relative ? 2 : 1;
     if ((rc = count_pass(pl, st))) return rc;
     HIP_TRY(hipStreamSynchronize(st));
     if (!pl->ncu) {

@@ -106,7 +106,7 @@ def lib():
         L.tdg_screen_list.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, C.c_int64, C.c_int64,
                                       C.POINTER(C.c_int64)]
         L.tdg_quartet_contribs.argtypes = [vp, vp, vp, vp, C.c_int32, vp, C.c_int64, vp, C.c_int32, vp]
-        L.tdg_fock.argtypes = [vp, vp, C.c_int32, vp, C.c_double, C.c_double, C.c_double, vp,
+        L.tdg_fock.argtypes = [vp, vp, C.c_int32, vp, C.c_double, C.c_double, C.c_double, C.c_int32, vp,
                                C.POINTER(Stats)]
         L.tdg_mlp_create.argtypes = [C.c_int, C.c_uint64, C.POINTER(vp)]
         L.tdg_mlp_destroy.argtypes = [vp]
@@ -224,19 +224,20 @@ class Plan:
                                           _ptr(q), precision, _ptr(out)))
         return out
 
-    def fock(self, B, cJ=1.0, cK=0.0, cKlr=0.0, stats=False):
-        """Host numpy B [n_bf, n_bf] -> host Fock-type matrix (synchronous); see tdg_fock."""
+    def fock(self, B, cJ=1.0, cK=0.0, cKlr=0.0, relative=False, stats=False):
+        """Host numpy B [n_bf, n_bf] -> host Fock-type matrix (synchronous); see tdg_fock
+        (relative: screening of B scaled to a largest element of one)."""
         B = np.ascontiguousarray(B, dtype=np.float64)
         n = self.n_bf
         if B.shape != (n, n):
             raise ValueError(f"B must be {n}x{n}, got {B.shape}")
         out = np.zeros((n, n))
         st = Stats()
-        _check(lib().tdg_fock(self._h, _ptr(B), 0, None, float(cJ), float(cK), float(cKlr), _ptr(out),
-                              C.byref(st) if stats else None))
+        _check(lib().tdg_fock(self._h, _ptr(B), 0, None, float(cJ), float(cK), float(cKlr), int(bool(relative)),
+                              _ptr(out), C.byref(st) if stats else None))
         return (out, st.as_dict()) if stats else out
 
-    def fock_device(self, B, out, cJ=1.0, cK=0.0, cKlr=0.0, stream=None, stats=False):
+    def fock_device(self, B, out, cJ=1.0, cK=0.0, cKlr=0.0, relative=False, stream=None, stats=False):
         """torch float64 device tensors B and out [n_bf, n_bf]; queued on `stream` (default:
         torch's current stream), with one wait on it for the screening counts."""
         import torch
@@ -246,8 +247,8 @@ class Plan:
                 raise ValueError("B and out must be contiguous float64 device tensors of shape (n_bf, n_bf)")
         s = (stream or torch.cuda.current_stream()).cuda_stream
         st = Stats()
-        _check(lib().tdg_fock(self._h, B.data_ptr(), 1, s, float(cJ), float(cK), float(cKlr), out.data_ptr(),
-                              C.byref(st) if stats else None))
+        _check(lib().tdg_fock(self._h, B.data_ptr(), 1, s, float(cJ), float(cK), float(cKlr), int(bool(relative)),
+                              out.data_ptr(), C.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
     def set_screen_model(self, model, log10_threshold=-12.0, tau_hi=1e-6):

@@ -108,12 +108,37 @@ def test_fock_zero_and_single_element(tdg, oracle_lib):
     assert _err(p.fock(E, *cf), ref) <= REL
 
 
+def test_fock_relative_screening(tdg, mol0, config0_parts):
+    """A Krylov-like vector shrunk by 2^-28 (a power of two, so that every bound scales
+    exactly): absolute screening at 1e-10 drops most quartets (config 0 keeps 2852 of 21092);
+    relative screening (B scaled to a unit largest element, F scaled back) keeps the
+    survivors of the unscaled matrix and returns its F times 2^-28."""
+    B, parts = config0_parts
+    cf = _coefs(mol0)["G_2e"]
+    ref = cf[0] * parts[0] + cf[1] * parts[1] + cf[2] * parts[2]
+    s = 2.0 ** -28
+    p = tdg.Plan(mol0, schwarz_tol=1e-10)
+    Bm = B / np.abs(0.5 * (B + B.T)).max()    # largest |Bs| element one
+    F1, st1 = p.fock(Bm, *cf, stats=True)
+    Fa, sta = p.fock(s * Bm, *cf, stats=True)
+    Fr, str_ = p.fock(s * Bm, *cf, relative=True, stats=True)
+    _say("relative screening: quartets", st1["quartets"], "absolute on the shrunk matrix", sta["quartets"],
+         "relative", str_["quartets"])
+    assert str_["quartets"] == st1["quartets"] and sta["quartets"] < st1["quartets"] // 4
+    assert np.abs(Fr - s * F1).max() <= 1e-13 * s * np.abs(F1).max()
+    refm = ref / np.abs(0.5 * (B + B.T)).max()
+    assert np.abs(Fr / s - refm).max() <= 1e-7
+
+
 def test_fock_errors(tdg):
     m = molecules.small_mixed()
     p = tdg.Plan(m, schwarz_tol=0.0)
     B = np.zeros((m.n_bf, m.n_bf))
     with pytest.raises(tdg.TdgError):
         p.fock(B, 1.0, 0.0, float("nan"))
+    q = tdg.Plan(m, schwarz_tol=0.0, terms=3, omega=0.0)
+    with pytest.raises(tdg.TdgError):
+        q.fock(B, 1.0, 0.0, 1.0)       # long-range exchange without omega
     with pytest.raises(ValueError):
         p.fock(np.zeros((3, 3)))
 
