@@ -311,10 +311,12 @@ int tdg_quartet_contribs(tdg_plan_t *plan, const double *P0, const double *PDelt
  * scaled back (the threshold becomes schwarz_tol max|Bs|): the normalisation of the
  * Krylov vectors before the Fock build discussed in section III.B, which keeps the shrinking
  * vectors of late Z-vector iterations from being screened away; 0 = absolute.  FP64
- * throughout, whatever the plan's precision.  stats may be NULL; when given, quartets,
+ * throughout, whatever the plan's precision.  The class kernels run side by side on the
+ * plan's streams as in tdg_grad_jk (joined back into hip_stream before the last step).
+ * stats may be NULL; when given, quartets,
  * prim_quartets, candidates, class_quartets, class_prim_quartets, class_ms (each Fock class
- * kernel timed alone: the call waits after every launch), chunks, ms_kernels and ms_total
- * are filled.
+ * kernel timed alone on hip_stream: the call waits after every launch), chunks, ms_kernels
+ * and ms_total are filled.
  * Errors: TDG_EINVAL (null pointers, non-finite coefficients, cKlr != 0 with omega <= 0,
  * relative not 0 or 1),
  * TDG_ENOMEM, TDG_EDEVICE. */

@@ -2623,15 +2623,42 @@ int tdg_fock(tdg_plan_t *pl, const double *B, int32_t ptr_kind, void *hip_stream
         Chunk ch;
         if ((rc = fill_items(pl, st, K0, K1, ch))) return rc;
         ++nchunks;
+        // class launches largest expected work first (primitive quartets x roots x
+        // (components + 30)), each to the least loaded of the plan's streams, forked from
+        // and joined back into the caller's stream; with stats every launch runs alone on
+        // the caller's stream and is timed
+        int order[kNumClasses], nord = 0;
+        double cost[kNumClasses] = {0.0};
         for (int c = 0; c < kNumClasses; ++c) {
-            const long long b = ch.seg_begin[c][0], e = ch.seg_end[c][0];
-            if (e <= b) continue;
-            fa.tasks = pl->d_tasks.p + b;
-            fa.ntasks = e - b;
+            const long long nq = ch.seg_end[c][0] - ch.seg_begin[c][0];
+            if (nq <= 0) continue;
+            int pb, pk;
+            class_pk(c, pb, pk);
+            const int L = kPairL[pb][0] + kPairL[pb][1] + kPairL[pk][0] + kPairL[pk][1];
+            const double prim = cls_q[c] > 0 ? (double)pl->h_prim[c] * nq / cls_q[c] : 0.0;
+            cost[c] = prim * (L / 2 + 1) * (class_ncomp(c) + 30.0);
+            order[nord++] = c;
+        }
+        std::stable_sort(order, order + nord, [&](int x, int y) { return cost[x] > cost[y]; });
+        const int nst = stats ? 1 : pl->nstreams;
+        if (nst > 1) {
+            HIP_TRY(hipEventRecord(pl->ev_fork, st));
+            for (int k = 0; k + 1 < nst; ++k) HIP_TRY(hipStreamWaitEvent(pl->aux[k], pl->ev_fork, 0));
+        }
+        double load[tdg_plan::kMaxAux + 1] = {0.0};
+        for (int oi = 0; oi < nord; ++oi) {
+            const int c = order[oi];
+            int k = 0;
+            for (int q = 1; q < nst; ++q)
+                if (load[q] < load[k]) k = q;
+            load[k] += cost[c];
+            hipStream_t sc = k == 0 ? st : pl->aux[k - 1];
+            fa.tasks = pl->d_tasks.p + ch.seg_begin[c][0];
+            fa.ntasks = ch.seg_end[c][0] - ch.seg_begin[c][0];
             if (stats) HIP_TRY(hipEventRecord(pl->ev0, st));
-            if (kFock[c](fa, lr, st, pl->ncu * kGridPerCU) != hipSuccess)
+            if (kFock[c](fa, lr, sc, pl->ncu * kGridPerCU) != hipSuccess)
                 return fail(TDG_EDEVICE, "Fock class %d launch failed", c);
-            if (stats) { // each class kernel timed alone (HIP events on the call's stream)
+            if (stats) {
                 HIP_TRY(hipEventRecord(pl->ev1, st));
                 HIP_TRY(hipEventSynchronize(pl->ev1));
                 float ms = 0.0f;
@@ -2639,6 +2666,10 @@ int tdg_fock(tdg_plan_t *pl, const double *B, int32_t ptr_kind, void *hip_stream
                 cls_ms[c] += ms;
                 kms += ms;
             }
+        }
+        for (int k = 0; k + 1 < nst; ++k) {
+            HIP_TRY(hipEventRecord(pl->ev_join[k], pl->aux[k]));
+            HIP_TRY(hipStreamWaitEvent(st, pl->ev_join[k], 0));
         }
         K0 = K1;
     }
