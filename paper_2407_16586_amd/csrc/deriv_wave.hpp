@@ -7,9 +7,9 @@
 //            four-centre recurrence and writes derivative-ready 2D tables to
 //            LDS: for every index quadruple (i<=la, j<=lb, k<=lc, l<=ld) the
 //            integral G and its B, C, D derivatives;
-//   stage 2: lanes split the Cartesian components; each lane keeps the
-//            symmetrised Gamma of its components in registers and reads
-//            12 table values per component and root.
+//   stage 2: lanes split the Cartesian components; each lane reads the
+//            symmetrised Gamma of its components (written to LDS once per
+//            quartet) and 12 table values per component and root.
 // The A derivative follows from translational invariance.
 #pragma once
 #include "deriv_kernel.hpp"
@@ -31,8 +31,9 @@ struct WaveClass {
     static constexpr int CH0 = CH_LDS < NSLOT ? CH_LDS : NSLOT;
     static constexpr int CH = CH0 * 3 <= kWave ? CH0 : kWave / 3;
     static constexpr int NCHUNK = (NSLOT + CH - 1) / CH;
-    static constexpr int WAVE_LDS = CH * TAB;            // elements per wave
-    static constexpr int WAVES = WAVE_LDS * FB * 4 <= 64 * 1024 ? 4 : 2;
+    static constexpr int GN = LR ? 2 * N : N;            // symmetrised Gamma (and Gamma^lr) of the quartet
+    static constexpr int WAVE_LDS = CH * TAB + GN;       // elements per wave
+    static constexpr int WAVES = WAVE_LDS * FB * 4 <= 64 * 1024 ? 4 : (WAVE_LDS * FB * 2 <= 64 * 1024 ? 2 : 1);
     static constexpr int BLOCK = WAVES * kWave;
     static constexpr int CPL = (N + kWave - 1) / kWave;  // components per lane
     static constexpr bool EARLY_PREFETCH = N <= 27;      // next ket record loaded ahead
@@ -50,6 +51,7 @@ k_deriv_wave(const DerivArgs a)
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     F *tab = s_tab + wave * K::WAVE_LDS;
+    F *sg = tab + CH * TAB; // Gamma of the wavefront's quartet, Gamma^lr behind it
     // block-level accumulation in LDS
     const bool use_lds = a.lds_atoms;
     if (use_lds) {
@@ -80,20 +82,18 @@ k_deriv_wave(const DerivArgs a)
         const int sa = M.pair_sa[bra], sb = M.pair_sb[bra], sc = M.pair_sa[ket], sd = M.pair_sb[ket];
         const double deg = (sa != sb ? 2.0 : 1.0) * (sc != sd ? 2.0 : 1.0) * (bra != ket ? 2.0 : 1.0);
         const int oa = M.shell_ao[sa], ob = M.shell_ao[sb], oc = M.shell_ao[sc], od = M.shell_ao[sd];
-        F gam[CPL][2];
+        // the quartet's symmetrised Gamma goes to LDS (in registers it would hold two values
+        // per component for the whole task beside the tables' addresses; the largest
+        // classes then spill)
         size_t rec[12];
         pair_records<LA, LB, LC, LD>(M.n_bf, oa, ob, oc, od, rec);
-#pragma unroll
-        for (int q = 0; q < CPL; ++q) {
-            gam[q][0] = gam[q][1] = F(0);
-            if (cok[q]) {
-                const int c = lane + q * kWave;
-                const int id = c % ND, ic = (c / ND) % NC, ib = (c / (ND * NC)) % NB, ia = c / (ND * NC * NB);
-                double gf, gl;
-                gamma_sym<LA, LB, LC, LD>(M, rec, ia, ib, ic, id, deg, gf, gl);
-                gam[q][0] = F(gf);
-                gam[q][1] = F(gl);
-            }
+#pragma unroll 1
+        for (int c = lane; c < N; c += kWave) {
+            const int id = c % ND, ic = (c / ND) % NC, ib = (c / (ND * NC)) % NB, ia = c / (ND * NC * NB);
+            double gf, gl;
+            gamma_sym<LA, LB, LC, LD>(M, rec, ia, ib, ic, id, deg, gf, gl);
+            sg[c] = F(gf);
+            if constexpr (LR) sg[N + c] = F(gl);
         }
         const int atA = M.shell_atom[sa], atB = M.shell_atom[sb], atC = M.shell_atom[sc], atD = M.shell_atom[sd];
         // stage-1 lane role
@@ -175,19 +175,19 @@ k_deriv_wave(const DerivArgs a)
                                                          F(zd2 * CDx), F(dc.g2), F(dc.g3), F(dc.g4));
                     }
                     wave_sync();
-#pragma unroll
+#pragma unroll 1
                     for (int s = 0; s < CH; ++s) {
                         const int slot2 = ch * CH + s;
                         if (slot2 >= NSLOT) break;
-                        const int set = slot2 / NR;
                         const F *T = tab + s * TAB;
+                        const F *G = sg + ((LR && slot2 >= NR) ? N : 0);
                         F pacc[9];
 #pragma unroll
                         for (int k = 0; k < 9; ++k) pacc[k] = F(0);
 #pragma unroll
                         for (int q = 0; q < CPL; ++q) {
                             if (!cok[q]) continue;
-                            const F gm = gam[q][LR ? set : 0];
+                            const F gm = G[lane + q * kWave];
                             const int ex = eoff[q][0], ey = eoff[q][1], ez = eoff[q][2];
                             const F vx = T[ex], vy = T[ey], vz = T[ez];
                             const F gz = gm * vz;
