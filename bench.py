@@ -88,6 +88,15 @@ def _executed_flops(cls, variant, prec, nq):
     return None
 
 
+def _fock_kernel_name(cls):
+    """The Fock-type matrix kernel a class runs (long-range term present)."""
+    n = 1
+    for l in cls:
+        n *= (l + 1) * (l + 2) // 2
+    layout = "k_fock_lane" if n <= 27 else ("k_fock_lane, lane pairs" if n <= 54 else "k_fock")
+    return f"{layout} {cls}"
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -294,7 +303,7 @@ def main():
                 "kernel_ms_one_stream": float(cms.sum()),
                 "max_abs_err_vs_oracle_blocks": err,
                 "coefs": cf, "density": gf["density"],
-                "roofline": {"bound": "alu", "kernel": f"k_fock{tdgrad.CLASSES[dom]}", "achieved": ach,
+                "roofline": {"bound": "alu", "kernel": _fock_kernel_name(tdgrad.CLASSES[dom]), "achieved": ach,
                              "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK_TFLOPS,
                              "traffic": None, "launch_quartets": int(st["class_quartets"][dom]),
                              "launch_prim_quartets": int(st["class_prim_quartets"][dom]),

@@ -273,12 +273,15 @@ __global__ void __launch_bounds__((FockClass<LA, LB, LC, LD, LR>::BLOCK)) k_fock
     }
 }
 
-// Lane layout for the classes with few components (N <= 27): one lane per shell quartet
+// Lane layout for the classes with few components: one lane per shell quartet (N <= 27)
 // evaluates every root of both kernels with its base tables in registers, keeps the N
 // contracted integrals of each kernel in registers, and forms the six output blocks
 // itself (compile-time indices throughout); the Rys table of the class sits in LDS.  No
-// wavefront synchronisation inside the task loop.
-template <int LA, int LB, int LC, int LD, bool LR>
+// wavefront synchronisation inside the task loop.  PAIR (long-range classes with
+// 27 < N <= 54): two neighbouring lanes per quartet, one per kernel (full range, long
+// range), so that each holds N integrals; they exchange them once, and the first forms the
+// Coulomb blocks, the second the exchange blocks.
+template <int LA, int LB, int LC, int LD, bool LR, bool PAIR = false>
 struct FockLane {
     static constexpr int L = LA + LB + LC + LD;
     static constexpr int NR = L / 2 + 1;
@@ -288,6 +291,10 @@ struct FockLane {
     static constexpr bool TAB_LDS = NR <= 3;
     static constexpr int TAB_N = TAB_LDS ? rys_table_size<NR>() : 1;
     static constexpr int BLOCK = 128;
+    static constexpr int LPQ = PAIR ? 2 : 1;          // lanes per quartet
+    static constexpr int QPB = BLOCK / LPQ;           // quartets per block and round
+    static constexpr int NV = (LR && !PAIR) ? 2 : 1;  // kernels a lane accumulates
+    static_assert(!PAIR || LR, "the paired layout splits the two kernels");
 };
 
 template <int LA, int LB, int LC, int LD>
@@ -299,11 +306,119 @@ __device__ __forceinline__ constexpr int fock_e(int c, int d)
            kCart.v[LD][id][d];
 }
 
+// The six output blocks of one quartet from its contracted integrals v0 (full range) and v1
+// (long range; read only when LR) into G with FP64 atomics.  Every lane of the wavefront
+// calls it; wave_j (uniform) enables the Coulomb part, cj says whether this lane forms the
+// Coulomb blocks, ck the exchange blocks.  J_ab is first summed over the wavefront when its
+// lanes share the bra pair (the tasks of a class are ordered by bra pair, so one atomic
+// replaces up to 64 on one address).
 template <int LA, int LB, int LC, int LD, bool LR>
+__device__ __forceinline__ void fock_lane_out(const FockArgs &a, bool valid, int bra, int ket, int sa, int sb, int sc,
+                                              int sd, bool cj, bool ck, bool wave_j, const double *v0,
+                                              const double *v1)
+{
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    const double deg = (sa != sb ? 2.0 : 1.0) * (sc != sd ? 2.0 : 1.0) * (bra != ket ? 2.0 : 1.0);
+    const double wJ = 0.25 * deg * a.cJ, wK = 0.125 * deg;
+    const int n = a.n_bf;
+    const int oa = a.shell_ao[sa], ob = a.shell_ao[sb], oc = a.shell_ao[sc], od = a.shell_ao[sd];
+    const double *Bcd = a.bmat + dens_rec(n, oc, NC, od), *Bab = a.bmat + dens_rec(n, oa, NA, ob);
+    const double *Bbd = a.bmat + dens_rec(n, ob, NB, od), *Bbc = a.bmat + dens_rec(n, ob, NB, oc);
+    const double *Bad = a.bmat + dens_rec(n, oa, NA, od), *Bac = a.bmat + dens_rec(n, oa, NA, oc);
+    const bool jl = valid && cj;
+#define V_(i, j, k, l) ((((i) * NB + (j)) * NC + (k)) * ND + (l))
+#define KV_(x) (a.cK * v0[x] + (LR ? a.cKlr * v1[x] : 0.0))
+    if (wave_j) {
+        const int bra0 = __shfl(bra, 0);
+        const bool same_bra = __all(!jl || bra == bra0);
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < NC; ++k)
+#pragma unroll
+                    for (int l = 0; l < ND; ++l) s += v0[V_(i, j, k, l)] * Bcd[k * ND + l];
+                s = jl ? wJ * s : 0.0;
+                if (same_bra) {
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+                    if ((threadIdx.x & (kWave - 1)) == 0 && s != 0.0)
+                        atomic_add_global(a.G + (size_t)(oa + i) * n + ob + j, s);
+                } else if (s != 0.0) {
+                    atomic_add_global(a.G + (size_t)(oa + i) * n + ob + j, s);
+                }
+            }
+        if (jl) {
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+#pragma unroll
+                for (int l = 0; l < ND; ++l) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int i = 0; i < NA; ++i)
+#pragma unroll
+                        for (int j = 0; j < NB; ++j) s += v0[V_(i, j, k, l)] * Bab[i * NB + j];
+                    if (s != 0.0) atomic_add_global(a.G + (size_t)(oc + k) * n + od + l, wJ * s);
+                }
+        }
+    }
+    if (ck && valid) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+#pragma unroll
+            for (int k = 0; k < NC; ++k) { // K_ac
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int l = 0; l < ND; ++l) s += KV_(V_(i, j, k, l)) * Bbd[j * ND + l];
+                if (s != 0.0) atomic_add_global(a.G + (size_t)(oa + i) * n + oc + k, wK * s);
+            }
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+#pragma unroll
+            for (int l = 0; l < ND; ++l) { // K_ad
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) s += KV_(V_(i, j, k, l)) * Bbc[j * NC + k];
+                if (s != 0.0) atomic_add_global(a.G + (size_t)(oa + i) * n + od + l, wK * s);
+            }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int k = 0; k < NC; ++k) { // K_bc
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < NA; ++i)
+#pragma unroll
+                    for (int l = 0; l < ND; ++l) s += KV_(V_(i, j, k, l)) * Bad[i * ND + l];
+                if (s != 0.0) atomic_add_global(a.G + (size_t)(ob + j) * n + oc + k, wK * s);
+            }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int l = 0; l < ND; ++l) { // K_bd
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < NA; ++i)
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) s += KV_(V_(i, j, k, l)) * Bac[i * NC + k];
+                if (s != 0.0) atomic_add_global(a.G + (size_t)(ob + j) * n + od + l, wK * s);
+            }
+    }
+#undef KV_
+#undef V_
+}
+
+template <int LA, int LB, int LC, int LD, bool LR, bool PAIR = false>
 __global__ void __launch_bounds__(128) k_fock_lane(const FockArgs a)
 {
-    using K = FockLane<LA, LB, LC, LD, LR>;
-    constexpr int NR = K::NR, N = K::N, NBASE = K::NBASE;
+    using K = FockLane<LA, LB, LC, LD, LR, PAIR>;
+    constexpr int NR = K::NR, N = K::N, NBASE = K::NBASE, NV = K::NV;
     constexpr int NA = K::NA, NB = K::NB, NC = K::NC, ND = K::ND;
     __shared__ double s_rys[K::TAB_N];
     if constexpr (K::TAB_LDS) {
@@ -312,11 +427,14 @@ __global__ void __launch_bounds__(128) k_fock_lane(const FockArgs a)
     }
     const double iom2 = LR ? 1.0 / (a.omega * a.omega) : 0.0;
     const bool doJ = a.cJ != 0.0, doK = a.cK != 0.0 || (LR && a.cKlr != 0.0);
-    const long long stride = (long long)gridDim.x * blockDim.x;
+    // PAIR: the odd lane of a pair evaluates the long-range kernel and forms the exchange blocks
+    const int half = PAIR ? (int)(threadIdx.x & 1) : 0;
+    const bool jrole = !PAIR || half == 0, krole = !PAIR || half == 1;
+    const long long stride = (long long)gridDim.x * K::QPB;
     // every lane of a block takes the same number of rounds (the J_ab reduction below is a
     // wavefront operation); lanes past the end carry no task
-    for (long long t0 = (long long)blockIdx.x * blockDim.x; t0 < a.ntasks; t0 += stride) {
-        const long long ti = t0 + threadIdx.x;
+    for (long long t0 = (long long)blockIdx.x * K::QPB; t0 < a.ntasks; t0 += stride) {
+        const long long ti = t0 + threadIdx.x / K::LPQ;
         const bool valid = ti < a.ntasks;
         const int2 tk = a.tasks[valid ? ti : a.ntasks - 1];
         const int bra = tk.x, ket = tk.y;
@@ -330,11 +448,11 @@ __global__ void __launch_bounds__(128) k_fock_lane(const FockArgs a)
             Cc[d] = a.coords[3 * atC + d];
             CD[d] = Cc[d] - a.coords[3 * atD + d];
         }
-        double v0[N], v1[LR ? N : 1];
+        double v[NV][N];
 #pragma unroll
-        for (int c = 0; c < N; ++c) v0[c] = 0.0;
+        for (int x = 0; x < NV; ++x)
 #pragma unroll
-        for (int c = 0; c < (LR ? N : 1); ++c) v1[c] = 0.0;
+            for (int c = 0; c < N; ++c) v[x][c] = 0.0;
         const int pb0 = a.pair_ppoff[bra], nbp = valid ? a.pair_npp[bra] : 0;
         const int pk0 = a.pair_ppoff[ket], nkp = a.pair_npp[ket];
         const double2 *rb = a.pp_rec + 4 * (size_t)pb0, *rk = a.pp_rec + 4 * (size_t)pk0;
@@ -362,9 +480,10 @@ __global__ void __launch_bounds__(128) k_fock_lane(const FockArgs a)
                 }
                 const double base_pref = cab * (ccd * iq) * sipq;
 #pragma unroll
-                for (int set = 0; set < (LR ? 2 : 1); ++set) {
+                for (int x = 0; x < NV; ++x) {
+                    const bool lr_set = PAIR ? half == 1 : (LR && x == 1);
                     double Tr = rho * pq2, eta = 1.0, seta = 1.0;
-                    if (set) {
+                    if (lr_set) {
                         seta = rsq64(1.0 + rho * iom2); // sqrt(omega^2 / (omega^2 + rho))
                         eta = seta * seta;
                         Tr *= eta;
@@ -374,7 +493,7 @@ __global__ void __launch_bounds__(128) k_fock_lane(const FockArgs a)
                         double u, w;
                         if constexpr (K::TAB_LDS) rys_root_lds<NR>(s_rys, Tr, r, u, w);
                         else rys_root<NR>(Tr, r, u, w);
-                        if (set) {
+                        if (lr_set) {
                             u *= eta;
                             w *= seta;
                         }
@@ -391,111 +510,29 @@ __global__ void __launch_bounds__(128) k_fock_lane(const FockArgs a)
                                                                 B10, B01, B00);
                         }
 #pragma unroll
-                        for (int c = 0; c < N; ++c) {
-                            const double v = I[0][fock_e<LA, LB, LC, LD>(c, 0)] * I[1][fock_e<LA, LB, LC, LD>(c, 1)] *
-                                             I[2][fock_e<LA, LB, LC, LD>(c, 2)];
-                            if (set) v1[LR ? c : 0] += v;
-                            else v0[c] += v;
-                        }
+                        for (int c = 0; c < N; ++c)
+                            v[x][c] += I[0][fock_e<LA, LB, LC, LD>(c, 0)] * I[1][fock_e<LA, LB, LC, LD>(c, 1)] *
+                                       I[2][fock_e<LA, LB, LC, LD>(c, 2)];
                     }
                 }
             }
         }
-        const double deg = (sa != sb ? 2.0 : 1.0) * (sc != sd ? 2.0 : 1.0) * (bra != ket ? 2.0 : 1.0);
-        const double wJ = 0.25 * deg * a.cJ, wK = 0.125 * deg;
-        double vK[N];
+        if constexpr (PAIR) {
+            // the pair's lanes swap their integrals: afterwards v[0] holds the full-range and
+            // v1 the long-range ones on the exchange lane (the Coulomb lane needs v[0] only)
+            double o[N];
 #pragma unroll
-        for (int c = 0; c < N; ++c) vK[c] = wK * (a.cK * v0[c] + (LR ? a.cKlr * v1[LR ? c : 0] : 0.0));
-        const int n = a.n_bf;
-        const int oa = a.shell_ao[sa], ob = a.shell_ao[sb], oc = a.shell_ao[sc], od = a.shell_ao[sd];
-        const double *Bcd = a.bmat + dens_rec(n, oc, NC, od), *Bab = a.bmat + dens_rec(n, oa, NA, ob);
-        const double *Bbd = a.bmat + dens_rec(n, ob, NB, od), *Bbc = a.bmat + dens_rec(n, ob, NB, oc);
-        const double *Bad = a.bmat + dens_rec(n, oa, NA, od), *Bac = a.bmat + dens_rec(n, oa, NA, oc);
-#define V_(i, j, k, l) ((((i) * NB + (j)) * NC + (k)) * ND + (l))
-        if (doJ) {
-            // J_ab: the tasks of a class segment are ordered by bra pair, so the lanes of a
-            // wavefront mostly share it; then the wavefront sums each element first and one
-            // lane adds it (instead of 64 atomic adds to one address)
-            const int bra0 = __shfl(bra, 0);
-            const bool same_bra = __all(!valid || bra == bra0);
+            for (int c = 0; c < N; ++c) o[c] = __shfl_xor(v[0][c], 1);
 #pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int j = 0; j < NB; ++j) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int k = 0; k < NC; ++k)
-#pragma unroll
-                        for (int l = 0; l < ND; ++l) s += v0[V_(i, j, k, l)] * Bcd[k * ND + l];
-                    s = valid ? wJ * s : 0.0;
-                    if (same_bra) {
-#pragma unroll
-                        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-                        if ((threadIdx.x & (kWave - 1)) == 0 && s != 0.0)
-                            atomic_add_global(a.G + (size_t)(oa + i) * n + ob + j, s);
-                    } else if (s != 0.0) {
-                        atomic_add_global(a.G + (size_t)(oa + i) * n + ob + j, s);
-                    }
-                }
-#pragma unroll
-            for (int k = 0; k < NC; ++k)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int i = 0; i < NA; ++i)
-#pragma unroll
-                        for (int j = 0; j < NB; ++j) s += v0[V_(i, j, k, l)] * Bab[i * NB + j];
-                    if (valid && s != 0.0) atomic_add_global(a.G + (size_t)(oc + k) * n + od + l, wJ * s);
-                }
+            for (int c = 0; c < N; ++c) {
+                const double mine = v[0][c];
+                v[0][c] = half ? o[c] : mine;
+                o[c] = half ? mine : 0.0;
+            }
+            fock_lane_out<LA, LB, LC, LD, LR>(a, valid, bra, ket, sa, sb, sc, sd, jrole, krole && doK, doJ, v[0], o);
+        } else {
+            fock_lane_out<LA, LB, LC, LD, LR>(a, valid, bra, ket, sa, sb, sc, sd, true, doK, doJ, v[0], v[NV - 1]);
         }
-        if (doK && valid) {
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int k = 0; k < NC; ++k) { // K_ac
-                    double s = 0.0;
-#pragma unroll
-                    for (int j = 0; j < NB; ++j)
-#pragma unroll
-                        for (int l = 0; l < ND; ++l) s += vK[V_(i, j, k, l)] * Bbd[j * ND + l];
-                    if (s != 0.0) atomic_add_global(a.G + (size_t)(oa + i) * n + oc + k, s);
-                }
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) { // K_ad
-                    double s = 0.0;
-#pragma unroll
-                    for (int j = 0; j < NB; ++j)
-#pragma unroll
-                        for (int k = 0; k < NC; ++k) s += vK[V_(i, j, k, l)] * Bbc[j * NC + k];
-                    if (s != 0.0) atomic_add_global(a.G + (size_t)(oa + i) * n + od + l, s);
-                }
-#pragma unroll
-            for (int j = 0; j < NB; ++j)
-#pragma unroll
-                for (int k = 0; k < NC; ++k) { // K_bc
-                    double s = 0.0;
-#pragma unroll
-                    for (int i = 0; i < NA; ++i)
-#pragma unroll
-                        for (int l = 0; l < ND; ++l) s += vK[V_(i, j, k, l)] * Bad[i * ND + l];
-                    if (s != 0.0) atomic_add_global(a.G + (size_t)(ob + j) * n + oc + k, s);
-                }
-#pragma unroll
-            for (int j = 0; j < NB; ++j)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) { // K_bd
-                    double s = 0.0;
-#pragma unroll
-                    for (int i = 0; i < NA; ++i)
-#pragma unroll
-                        for (int k = 0; k < NC; ++k) s += vK[V_(i, j, k, l)] * Bac[i * NC + k];
-                    if (s != 0.0) atomic_add_global(a.G + (size_t)(ob + j) * n + od + l, s);
-                }
-        }
-#undef V_
     }
 }
 
