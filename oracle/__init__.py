@@ -84,10 +84,57 @@ def _p(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
+def sph_transform(mol):
+    """T [n_functions, n_cart] mapping the unit-normalised Cartesian functions of every shell to
+    the caller's functions: identity for s, p and Cartesian d; for a d shell of a spherical
+    basis the five real solid harmonics r^2 Y_2m (m = -2..2) in the order xy, yz, z^2, xz,
+    x^2 - y^2, each scaled to unit norm.  With unit-normalised Cartesian components
+    (order xx, xy, xz, yy, yz, zz) the squared components overlap as <xx|yy> = 1/3, so
+    (xx - yy) has norm^2 4/3 and (2zz - xx - yy) norm^2 4."""
+    ls = np.asarray(mol.shell_l)
+    ncart = (ls + 1) * (ls + 2) // 2
+    sph = bool(getattr(mol, "spherical", False))
+    nfun = np.where((ls == 2) & sph, 5, ncart)
+    T = np.zeros((int(nfun.sum()), int(ncart.sum())))
+    r, c = 0, 0
+    for l, nf, nc in zip(ls, nfun, ncart):
+        if sph and l == 2:
+            xx, xy, xz, yy, yz, zz = range(6)
+            blk = np.zeros((5, 6))
+            blk[0, xy] = 1.0
+            blk[1, yz] = 1.0
+            blk[2, [zz, xx, yy]] = [1.0, -0.5, -0.5]
+            blk[3, xz] = 1.0
+            blk[4, [xx, yy]] = [np.sqrt(3.0) / 2.0, -np.sqrt(3.0) / 2.0]
+        else:
+            blk = np.eye(nc)
+        T[r:r + nf, c:c + nc] = blk
+        r, c = r + nf, c + nc
+    return T
+
+
+def _cart_view(mol):
+    """(Cartesian molecule, T, caller's function offsets): for a spherical basis the same shells
+    with Cartesian AO offsets in shell order (the caller's functions are assumed in shell
+    order, as the stored generators write them); for a Cartesian basis the molecule itself."""
+    if not getattr(mol, "spherical", False):
+        return mol, None
+    import dataclasses
+    ls = np.asarray(mol.shell_l)
+    ncart = (ls + 1) * (ls + 2) // 2
+    nfun = np.where(ls == 2, 5, ncart)
+    if not np.array_equal(np.asarray(mol.shell_ao_off), np.concatenate([[0], np.cumsum(nfun)[:-1]])):
+        raise ValueError("spherical oracle basis: functions must be in shell order")
+    off = np.ascontiguousarray(np.concatenate([[0], np.cumsum(ncart)[:-1]]), dtype=np.int32)
+    cm = dataclasses.replace(mol, shell_ao_off=off, spherical=False, P0=None, PD=None, R=None)
+    return cm, sph_transform(mol)
+
+
 class _Bound:
-    """Keeps the numpy arrays behind a Basis struct alive."""
+    """Keeps the numpy arrays behind a Basis struct alive (Cartesian functions)."""
 
     def __init__(self, mol, coords=None):
+        mol = _cart_view(mol)[0]
         c = np.ascontiguousarray(mol.coords if coords is None else coords, dtype=np.float64)
         self.keep = [c, mol.shell_atom, mol.shell_l, mol.shell_nprim, mol.shell_prim_off,
                      mol.shell_ao_off, mol.exps, mol.coefs]
@@ -103,8 +150,14 @@ def _params(mol, tau=0.0, terms=7, nthreads=0, omega=None, alpha=None, beta=None
 
 
 def _dens(mol, P0=None, PD=None, R=None):
+    """The densities on the Cartesian functions: X_cart = T^T X T for a spherical basis (each
+    density is a bilinear form in the functions of its two indices)."""
     f = lambda x, d: np.ascontiguousarray(d if x is None else x, dtype=np.float64)
-    return f(P0, mol.P0), f(PD, mol.PD), f(R, mol.R)
+    out = f(P0, mol.P0), f(PD, mol.PD), f(R, mol.R)
+    T = _cart_view(mol)[1]
+    if T is None:
+        return out
+    return tuple(np.ascontiguousarray(T.T @ x @ T) for x in out)
 
 
 def _check(rc, what):
@@ -192,7 +245,19 @@ def screen_select(mol, tau, keep=True, nthreads=0, cap=None, P0=None, PD=None, R
 
 
 def fock_blocks(mol, B, pairs, cJ=1.0, cK=0.0, cKlr=0.0, omega=None, nthreads=0):
-    """Blocks F[a, b] of the Fock-type matrix for shell pairs [n, 2]; list of arrays."""
+    """Blocks F[a, b] of the Fock-type matrix for shell pairs [n, 2]; list of arrays (in the
+    caller's functions: for a spherical basis T_a F_cart T_b^T with B_cart = T^T B T)."""
+    cm, T = _cart_view(mol)
+    if T is not None:
+        Bc = T.T @ np.asarray(B, dtype=np.float64) @ T
+        blocks = fock_blocks(cm, Bc, pairs, cJ, cK, cKlr, mol.omega if omega is None else omega, nthreads)
+        ls = np.asarray(mol.shell_l)
+        ncart = (ls + 1) * (ls + 2) // 2
+        nfun = np.where(ls == 2, 5, ncart)
+        fo, co = np.concatenate([[0], np.cumsum(nfun)]), np.concatenate([[0], np.cumsum(ncart)])
+        Tb = lambda s: T[fo[s]:fo[s + 1], co[s]:co[s + 1]]
+        pr = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+        return [Tb(a) @ blk @ Tb(b).T for (a, b), blk in zip(pr, blocks)]
     bb = _Bound(mol)
     B = np.ascontiguousarray(B, dtype=np.float64)
     pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
@@ -214,7 +279,7 @@ def fock(mol, B, cJ=1.0, cK=0.0, cKlr=0.0, omega=None, nthreads=0):
     pairs = np.array([(a, b) for a in range(ns) for b in range(ns)], dtype=np.int32)
     blocks = fock_blocks(mol, B, pairs, cJ, cK, cKlr, omega, nthreads)
     F = np.zeros((mol.n_bf, mol.n_bf))
-    nc = (mol.shell_l + 1) * (mol.shell_l + 2) // 2
+    nc = np.array([blk.shape[0] for blk in blocks[::ns]])
     for (a, b), blk in zip(pairs, blocks):
         oa, ob = mol.shell_ao_off[a], mol.shell_ao_off[b]
         F[oa:oa + nc[a], ob:ob + nc[b]] = blk
@@ -230,6 +295,10 @@ def schwarz(mol):
 
 
 def eri_tensor(mol, op=0, omega=None):
+    cm, T = _cart_view(mol)
+    if T is not None:  # (mu nu|lam sig) in the caller's functions
+        Tc = eri_tensor(cm, op, mol.omega if omega is None else omega)
+        return np.einsum("ai,bj,ck,dl,ijkl->abcd", T, T, T, T, Tc, optimize=True)
     bb = _Bound(mol)
     n = mol.n_bf
     out = np.zeros((n, n, n, n))

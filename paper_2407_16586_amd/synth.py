@@ -92,6 +92,7 @@ class Molecule:
     omega: float = OMEGA
     alpha: float = ALPHA_SR
     beta: float = ALPHA_LR - ALPHA_SR
+    spherical: bool = False     # d shells as 5 real solid harmonics (shell_ao_off counts 5)
 
     @property
     def n_atoms(self) -> int:
@@ -107,7 +108,8 @@ class Molecule:
 
     @property
     def n_bf(self) -> int:
-        return int(self.shell_ao_off[-1] + ncart(int(self.shell_l[-1])))
+        nf = lambda l: 5 if (self.spherical and l == 2) else ncart(l)
+        return int(max(o + nf(int(l)) for o, l in zip(self.shell_ao_off, self.shell_l)))
 
     def subset_check(self) -> None:
         assert self.coords.dtype == np.float64 and self.coords.shape[1] == 3
@@ -330,6 +332,24 @@ def config4(with_dens: bool = True) -> Molecule:
     electrons = int(Z.sum())
     return _assemble("1500-atom droplet", rng, coords, Z, n_occ=electrons // 2,
                      with_dens=with_dens)
+
+
+def spherical_copy(mol: Molecule, seed: int = 0) -> Molecule:
+    """The same geometry and shells with d shells as 5 real solid harmonics (functions in shell
+    order) and fresh seeded densities of the smaller size: P0 = 2 C_o C_o^T from random
+    orthonormal orbitals, a symmetric PDelta and a general R, of the magnitudes the
+    Cartesian generators use."""
+    ls = np.asarray(mol.shell_l)
+    nf = np.where(ls == 2, 5, (ls + 1) * (ls + 2) // 2)
+    off = np.ascontiguousarray(np.concatenate([[0], np.cumsum(nf)[:-1]]), dtype=np.int32)
+    out = dataclasses.replace(mol, name=mol.name + " (spherical d)", shell_ao_off=off, spherical=True,
+                              P0=None, PD=None, R=None)
+    n = int(nf.sum())
+    rng = np.random.default_rng(seed)
+    n_occ = max(1, min(mol.n_occ, n // 2))
+    P0, PD, R = _densities(rng, n, n_occ)[:3]
+    out.P0, out.PD, out.R = P0, PD, R
+    return out
 
 
 def random_molecule(n_heavy: int, n_h: int, seed: int, box: float | None = None,
