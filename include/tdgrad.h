@@ -77,6 +77,14 @@ typedef struct {
     int32_t n_prims;
     const double *exps;            /* [n_prims] Gaussian exponents zeta > 0 */
     const double *coefs;           /* [n_prims] contraction coefficients of unnormalised primitives */
+    int32_t spherical;             /* 0: Cartesian functions, ncart(l) per shell (eq cartG);
+                                      1: d shells as the five real solid harmonics (section II.C
+                                      names both forms), order xy, yz, z^2, xz, x^2-y^2 (m = -2..2),
+                                      each normalised to one; s and p shells are the same in both.
+                                      shell_ao_off, the density and the Fock-type matrix then count
+                                      2l+1 functions per d shell; the library works on the Cartesian
+                                      functions internally (densities transformed on entry, the
+                                      Fock-type matrix on exit; the gradient is unchanged by it) */
 } tdg_basis_t;
 
 #define TDG_MAX_NPRIM 16

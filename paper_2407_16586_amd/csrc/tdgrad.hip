@@ -208,6 +208,11 @@ struct tdg_plan {
     // the accumulator G of F = ang (G + G^T) ang
     int screen_fock = 0;
     DevBuf<double> d_fockG;
+    // the caller's functions: Cartesian (sph = 0: the internal layout itself) or with d shells
+    // as real solid harmonics (sph = 1: internal Cartesian offsets are cumulative in shell order)
+    int sph = 0, n_user = 0;
+    std::vector<int> shell_ao_user;
+    DevBuf<int> d_shell_ao_user, d_ao_shell_user; // caller's AO offset per shell, shell per caller AO
     // host-side state of the current call
     std::vector<int> h_cnt, h_cnt32;
     std::vector<unsigned long long> h_prim, h_cand;
@@ -330,30 +335,73 @@ __device__ __forceinline__ double block_bound(const BlkMax &ab, const BlkMax *bm
     return m;
 }
 
+// Real solid-harmonic d functions in terms of the unit-normalised Cartesian d components
+// (xx, xy, xz, yy, yz, zz): xy, yz, (2 zz - xx - yy)/2, xz, (sqrt 3 / 2)(xx - yy), each of
+// unit norm (the Cartesian components overlap as <xx|yy> = 1/3, <xx|xx> = 1).
+// sph_coef(l, sph, p, i): coefficient of Cartesian component i in function p of a shell of
+// momentum l (identity for s, p and for Cartesian d).
+__device__ __forceinline__ double sph_coef(int l, int sph, int p, int i)
+{
+    if (l != 2 || !sph) return p == i ? 1.0 : 0.0;
+    constexpr double h = 0.5, r3h = 0.86602540378443864676; // 1/2, sqrt(3)/2
+    switch (p) {
+    case 0: return i == 1 ? 1.0 : 0.0;                                   // xy
+    case 1: return i == 4 ? 1.0 : 0.0;                                   // yz
+    case 2: return i == 5 ? 1.0 : ((i == 0 || i == 3) ? -h : 0.0);       // z^2
+    case 3: return i == 2 ? 1.0 : 0.0;                                   // xz
+    default: return i == 0 ? r3h : (i == 3 ? -r3h : 0.0);                // x^2 - y^2
+    }
+}
+__device__ __forceinline__ int nfun(int l, int sph) { return (l == 2 && sph) ? 5 : ncart(l); }
+
+// Cartesian element (i, j) of the block (a, c) of a caller matrix X (dimension n_in, caller
+// offsets ua, uc): X_cart = T_a^T X T_c for solid-harmonic shells, X itself otherwise.
+__device__ __forceinline__ double cart_elem(const double *X, int n_in, int la, int ua, int lc, int uc, int sph, int i,
+                                            int j)
+{
+    if (!sph || (la != 2 && lc != 2)) return X[(size_t)(ua + i) * n_in + uc + j];
+    double v = 0.0;
+    const int fa = nfun(la, sph), fc = nfun(lc, sph);
+    for (int p = 0; p < fa; ++p) {
+        const double tp = sph_coef(la, sph, p, i);
+        if (tp == 0.0) continue;
+        for (int q = 0; q < fc; ++q) {
+            const double tq = sph_coef(lc, sph, q, j);
+            if (tq != 0.0) v += tp * X[(size_t)(ua + p) * n_in + uc + q] * tq;
+        }
+    }
+    return v;
+}
+
 // One thread per ordered shell pair (a, c): the pair's record of the shell-blocked
 // densities (P, D = P0 + 2 PDelta and R blocks, angular factors folded in; layout in
 // deriv_kernel.hpp) and the block maxima used by the screening bound.
 __global__ void k_density_prep(int n_shells, int n_bf, const int *shell_l, const int *shell_ao, const double *ang,
                                const double *P0, const double *PD, const double *R, double *dens, BlkMax *bmax,
-                               unsigned long long *mx)
+                               unsigned long long *mx, int sph, int n_in, const int *shell_ao_in)
 {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)n_shells * n_shells) return;
     const int a = (int)(idx / n_shells), c = (int)(idx % n_shells);
-    const int oa = shell_ao[a], oc = shell_ao[c], na = ncart(shell_l[a]), nc = ncart(shell_l[c]);
+    const int la = shell_l[a], lc = shell_l[c];
+    const int oa = shell_ao[a], oc = shell_ao[c], na = ncart(la), nc = ncart(lc);
+    // caller layout: the same offsets for Cartesian functions, else the caller's
+    const int ua = sph ? shell_ao_in[a] : oa, uc = sph ? shell_ao_in[c] : oc;
     double *rec = dens + dens_rec(n_bf, oa, na, oc);
     double vp = 0.0, vd = 0.0, vr = 0.0;
     for (int i = 0; i < na; ++i)
         for (int j = 0; j < nc; ++j) {
-            const size_t ij = (size_t)(oa + i) * n_bf + (oc + j), ji = (size_t)(oc + j) * n_bf + (oa + i);
-            const double p = P0[ij], d = P0[ij] + 2.0 * PD[ij], rr = R[ij];
+            const double p = cart_elem(P0, n_in, la, ua, lc, uc, sph, i, j);
+            const double d = p + 2.0 * cart_elem(PD, n_in, la, ua, lc, uc, sph, i, j);
+            const double rr = cart_elem(R, n_in, la, ua, lc, uc, sph, i, j);
+            const double rt = cart_elem(R, n_in, lc, uc, la, ua, sph, j, i);
             const double s = ang[oa + i] * ang[oc + j];
             rec[i * nc + j] = s * p;
             rec[na * nc + i * nc + j] = s * d;
             rec[2 * na * nc + i * nc + j] = s * rr;
             vp = fmax(vp, fabs(p));
             vd = fmax(vd, fabs(d));
-            vr = fmax(vr, fmax(fabs(rr), fabs(R[ji])));
+            vr = fmax(vr, fmax(fabs(rr), fabs(rt)));
         }
     BlkMax bm;
     bm.p = vp; bm.d = vd; bm.r = vr; bm.pad = 0.0;
@@ -369,17 +417,21 @@ __global__ void k_density_prep(int n_shells, int n_bf, const int *shell_l, const
 // largest |Bs| of the six blocks a quartet reads; mx receives the square root of the
 // largest |Bs| (its square scales the prefix cut).
 __global__ void k_fock_prep(int n_shells, int n_bf, const int *shell_l, const int *shell_ao, const double *ang,
-                            const double *B, double *dens, BlkMax *bmax, unsigned long long *mx)
+                            const double *B, double *dens, BlkMax *bmax, unsigned long long *mx, int sph, int n_in,
+                            const int *shell_ao_in)
 {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)n_shells * n_shells) return;
     const int a = (int)(idx / n_shells), c = (int)(idx % n_shells);
-    const int oa = shell_ao[a], oc = shell_ao[c], na = ncart(shell_l[a]), nc = ncart(shell_l[c]);
+    const int la = shell_l[a], lc = shell_l[c];
+    const int oa = shell_ao[a], oc = shell_ao[c], na = ncart(la), nc = ncart(lc);
+    const int ua = sph ? shell_ao_in[a] : oa, uc = sph ? shell_ao_in[c] : oc;
     double *rec = dens + dens_rec(n_bf, oa, na, oc);
     double vb = 0.0;
     for (int i = 0; i < na; ++i)
         for (int j = 0; j < nc; ++j) {
-            const double b = 0.5 * (B[(size_t)(oa + i) * n_bf + oc + j] + B[(size_t)(oc + j) * n_bf + oa + i]);
+            const double b = 0.5 * (cart_elem(B, n_in, la, ua, lc, uc, sph, i, j) +
+                                    cart_elem(B, n_in, lc, uc, la, ua, sph, j, i));
             rec[i * nc + j] = ang[oa + i] * ang[oc + j] * b;
             vb = fmax(vb, fabs(b));
         }
@@ -389,13 +441,35 @@ __global__ void k_fock_prep(int n_shells, int n_bf, const int *shell_l, const in
     atomicMax(mx, (unsigned long long)__double_as_longlong(sqrt(vb)));
 }
 
-// F = ang (G + G^T) ang, one thread per element
-__global__ void k_fock_finish(int n_bf, const double *ang, const double *G, double *F)
+// F = ang (G + G^T) ang, one thread per element; with solid-harmonic d shells the element
+// (mu, nu) of the caller's matrix is T_a F_cart T_c^T over the Cartesian components of the
+// two shells (mu in shell a, nu in shell c)
+__global__ void k_fock_finish(int n_bf, const double *ang, const double *G, double *F, int sph, int n_out,
+                              const int *ao_shell_out, const int *shell_ao_out, const int *shell_ao,
+                              const int *shell_l)
 {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long long)n_bf * n_bf) return;
-    const int i = (int)(idx / n_bf), j = (int)(idx % n_bf);
-    F[idx] = ang[i] * ang[j] * (G[idx] + G[(size_t)j * n_bf + i]);
+    if (idx >= (long long)n_out * n_out) return;
+    const int mu = (int)(idx / n_out), nu = (int)(idx % n_out);
+    if (!sph) {
+        F[idx] = ang[mu] * ang[nu] * (G[idx] + G[(size_t)nu * n_bf + mu]);
+        return;
+    }
+    const int a = ao_shell_out[mu], c = ao_shell_out[nu];
+    const int la = shell_l[a], lc = shell_l[c], oa = shell_ao[a], oc = shell_ao[c];
+    const int p = mu - shell_ao_out[a], q = nu - shell_ao_out[c];
+    double v = 0.0;
+    for (int i = 0; i < ncart(la); ++i) {
+        const double tp = sph_coef(la, sph, p, i);
+        if (tp == 0.0) continue;
+        for (int j = 0; j < ncart(lc); ++j) {
+            const double tq = sph_coef(lc, sph, q, j);
+            if (tq == 0.0) continue;
+            const size_t ij = (size_t)(oa + i) * n_bf + oc + j, ji = (size_t)(oc + j) * n_bf + oa + i;
+            v += tp * tq * ang[oa + i] * ang[oc + j] * (G[ij] + G[ji]);
+        }
+    }
+    F[idx] = v;
 }
 
 // ======================================================================= screening and task generation
@@ -904,15 +978,30 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
     pl->n_prims = b->n_prims;
     pl->shell_atom.assign(b->shell_atom, b->shell_atom + ns);
     pl->shell_l.assign(b->shell_l, b->shell_l + ns);
-    pl->shell_ao.assign(b->shell_ao_off, b->shell_ao_off + ns);
+    pl->sph = b->spherical ? 1 : 0;
+    pl->shell_ao_user.assign(b->shell_ao_off, b->shell_ao_off + ns);
+    if (pl->sph) { // internal Cartesian functions, cumulative in shell order
+        pl->shell_ao.resize(ns);
+        int o = 0;
+        for (int s = 0; s < ns; ++s) {
+            pl->shell_ao[s] = o;
+            o += ncart(b->shell_l[s]);
+        }
+    } else {
+        pl->shell_ao = pl->shell_ao_user;
+    }
     pl->b_coords.assign(b->coords, b->coords + 3 * b->n_atoms);
     pl->b_exps.assign(b->exps, b->exps + b->n_prims);
     pl->b_coefs.assign(b->coefs, b->coefs + b->n_prims);
     pl->b_nprim.assign(b->shell_nprim, b->shell_nprim + ns);
     pl->b_primoff.assign(b->shell_prim_off, b->shell_prim_off + ns);
-    int nbf = 0;
-    for (int s = 0; s < ns; ++s) nbf = std::max(nbf, b->shell_ao_off[s] + ncart(b->shell_l[s]));
+    int nbf = 0, nuser = 0;
+    for (int s = 0; s < ns; ++s) {
+        nbf = std::max(nbf, pl->shell_ao[s] + ncart(b->shell_l[s]));
+        nuser = std::max(nuser, b->shell_ao_off[s] + ((pl->sph && b->shell_l[s] == 2) ? 5 : ncart(b->shell_l[s])));
+    }
     pl->n_bf = nbf;
+    pl->n_user = nuser;
 
     // normalised coefficients and per-AO angular factors
     std::vector<double> coef(b->n_prims);
@@ -923,7 +1012,7 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
     for (int s = 0; s < ns; ++s)
         for (int k = 0; k < ncart(b->shell_l[s]); ++k) {
             const int *t = kCart.v[b->shell_l[s]][k];
-            ang[b->shell_ao_off[s] + k] = ang_factor(t[0], t[1], t[2]);
+            ang[pl->shell_ao[s] + k] = ang_factor(t[0], t[1], t[2]);
         }
 
     // canonical pairs (first shell has the higher l; equal l: higher index first)
@@ -983,6 +1072,13 @@ static int build_plan(tdg_plan *pl, const tdg_basis_t *b)
         (rc = pl->d_pp_Py.upload(pp[2])) || (rc = pl->d_pp_Pz.upload(pp[3])) || (rc = pl->d_pp_c.upload(pp[4])) ||
         (rc = pl->d_ang.upload(ang)))
         return rc;
+    if (pl->sph) {
+        std::vector<int> ao_shell(nuser, 0);
+        for (int s = 0; s < ns; ++s)
+            for (int k = 0; k < (b->shell_l[s] == 2 ? 5 : ncart(b->shell_l[s])); ++k) ao_shell[b->shell_ao_off[s] + k] = s;
+        if ((rc = pl->d_shell_ao_user.upload(pl->shell_ao_user)) || (rc = pl->d_ao_shell_user.upload(ao_shell)))
+            return rc;
+    }
 
     // Schwarz per pair class: pairs grouped by class for the templated kernel
     std::vector<int> order(np);
@@ -1174,6 +1270,7 @@ static int check_basis(const tdg_basis_t *b)
         !b->shell_ao_off || !b->exps || !b->coefs)
         return fail(TDG_EINVAL, "null pointer in basis");
     if (b->n_atoms <= 0 || b->n_shells <= 0 || b->n_prims <= 0) return fail(TDG_EINVAL, "empty basis");
+    if (b->spherical != 0 && b->spherical != 1) return fail(TDG_EINVAL, "spherical must be 0 or 1");
     for (int s = 0; s < b->n_shells; ++s) {
         if (b->shell_l[s] < 0 || b->shell_l[s] > 2) return fail(TDG_EUNSUPPORTED, "shell %d has l=%d (max 2)", s, b->shell_l[s]);
         if (b->shell_nprim[s] < 1 || b->shell_nprim[s] > TDG_MAX_NPRIM)
@@ -1295,7 +1392,7 @@ int tdg_plan_set_streams(tdg_plan_t *pl, int32_t streams)
 int tdg_plan_dims(const tdg_plan_t *pl, int32_t *n_bf, int32_t *n_atoms, int32_t *n_shells)
 {
     if (!pl) return fail(TDG_EINVAL, "null plan");
-    if (n_bf) *n_bf = pl->n_bf;
+    if (n_bf) *n_bf = pl->n_user;
     if (n_atoms) *n_atoms = pl->n_atoms;
     if (n_shells) *n_shells = pl->n_shells;
     return TDG_OK;
@@ -1373,7 +1470,7 @@ static int prep_density(tdg_plan *pl, const double *P0, const double *PD, const 
                           hipStream_t st)
 {
     const int nbf = pl->n_bf, ns = pl->n_shells;
-    const size_t nn = (size_t)nbf * nbf;
+    const size_t nn = (size_t)pl->n_user * pl->n_user; // caller's matrices
     int rc;
     const double *dP0 = P0, *dPD = PD, *dR = R;
     if (ptr_kind == 0) {
@@ -1393,7 +1490,7 @@ static int prep_density(tdg_plan *pl, const double *P0, const double *PD, const 
     const long long nblk = (long long)ns * ns;
     hipLaunchKernelGGL(k_density_prep, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, ns, nbf,
                        pl->d_shell_l.p, pl->d_shell_ao.p, pl->d_ang.p, dP0, dPD, dR, pl->d_dens.p, pl->d_bmax.p,
-                       pl->d_mx.p);
+                       pl->d_mx.p, pl->sph, pl->n_user, pl->d_shell_ao_user.p);
     HIP_TRY(hipGetLastError());
     return TDG_OK;
 }
@@ -2331,7 +2428,8 @@ int tdg_plan_update_coords(tdg_plan_t *pl, const double *coords)
     b.shell_l = pl->shell_l.data();
     b.shell_nprim = pl->b_nprim.data();
     b.shell_prim_off = pl->b_primoff.data();
-    b.shell_ao_off = pl->shell_ao.data();
+    b.shell_ao_off = pl->shell_ao_user.data();
+    b.spherical = pl->sph;
     b.n_prims = pl->n_prims;
     b.exps = pl->b_exps.data();
     b.coefs = pl->b_coefs.data();
@@ -2559,12 +2657,13 @@ int tdg_fock(tdg_plan_t *pl, const double *B, int32_t ptr_kind, void *hip_stream
     hipStream_t st = (hipStream_t)hip_stream;
     HIP_TRY(hipSetDevice(pl->device));
     const int nbf = pl->n_bf, ns = pl->n_shells;
-    const size_t nn = (size_t)nbf * nbf;
+    const size_t nn = (size_t)nbf * nbf;            // internal Cartesian accumulator
+    const size_t nu = (size_t)pl->n_user * pl->n_user; // caller's B and F
     int rc;
     const double *dB = B;
     if (ptr_kind == 0) {
-        if ((rc = pl->d_in.alloc(3 * nn))) return rc;
-        HIP_TRY(hipMemcpyAsync(pl->d_in.p, B, nn * 8, hipMemcpyHostToDevice, st));
+        if ((rc = pl->d_in.alloc(3 * nu))) return rc;
+        HIP_TRY(hipMemcpyAsync(pl->d_in.p, B, nu * 8, hipMemcpyHostToDevice, st));
         dB = pl->d_in.p;
     }
     if ((rc = pl->d_fockG.alloc(nn))) return rc;
@@ -2574,7 +2673,8 @@ int tdg_fock(tdg_plan_t *pl, const double *B, int32_t ptr_kind, void *hip_stream
     hipLaunchKernelGGL(k_zero, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, pl->d_fockG.p, (long long)nn);
     const long long nblk = (long long)ns * ns;
     hipLaunchKernelGGL(k_fock_prep, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, ns, nbf, pl->d_shell_l.p,
-                       pl->d_shell_ao.p, pl->d_ang.p, dB, pl->d_dens.p, pl->d_bmax.p, pl->d_mx.p);
+                       pl->d_shell_ao.p, pl->d_ang.p, dB, pl->d_dens.p, pl->d_bmax.p, pl->d_mx.p, pl->sph,
+                       pl->n_user, pl->d_shell_ao_user.p);
     HIP_TRY(hipGetLastError());
     // the screening passes of this call keep one-centre quartets and route nothing to FP32
     struct FockScreen {
@@ -2674,12 +2774,13 @@ int tdg_fock(tdg_plan_t *pl, const double *B, int32_t ptr_kind, void *hip_stream
         K0 = K1;
     }
     double *dF = F;
-    if (ptr_kind == 0) dF = pl->d_in.p + nn; // staging slot behind the copy of B
-    hipLaunchKernelGGL(k_fock_finish, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, nbf, pl->d_ang.p,
-                       pl->d_fockG.p, dF);
+    if (ptr_kind == 0) dF = pl->d_in.p + nu; // staging slot behind the copy of B
+    hipLaunchKernelGGL(k_fock_finish, dim3((unsigned)((nu + 255) / 256)), dim3(256), 0, st, nbf, pl->d_ang.p,
+                       pl->d_fockG.p, dF, pl->sph, pl->n_user, pl->d_ao_shell_user.p, pl->d_shell_ao_user.p,
+                       pl->d_shell_ao.p, pl->d_shell_l.p);
     HIP_TRY(hipGetLastError());
     if (ptr_kind == 0) {
-        HIP_TRY(hipMemcpyAsync(F, dF, nn * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(F, dF, nu * 8, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
     if (stats) {

@@ -41,7 +41,7 @@ class Basis(C.Structure):
                 ("n_shells", C.c_int32), ("shell_atom", C.c_void_p), ("shell_l", C.c_void_p),
                 ("shell_nprim", C.c_void_p), ("shell_prim_off", C.c_void_p),
                 ("shell_ao_off", C.c_void_p), ("n_prims", C.c_int32),
-                ("exps", C.c_void_p), ("coefs", C.c_void_p)]
+                ("exps", C.c_void_p), ("coefs", C.c_void_p), ("spherical", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -146,7 +146,8 @@ class Plan:
         self._keep.append(np.ascontiguousarray(mol.coefs, dtype=np.float64))
         k = self._keep
         b = Basis(mol.n_atoms, _ptr(k[0]), mol.n_shells, _ptr(k[1]), _ptr(k[2]), _ptr(k[3]),
-                  _ptr(k[4]), _ptr(k[5]), mol.n_prims, _ptr(k[6]), _ptr(k[7]))
+                  _ptr(k[4]), _ptr(k[5]), mol.n_prims, _ptr(k[6]), _ptr(k[7]),
+                  int(getattr(mol, "spherical", 0)))
         self.params = Params(mol.omega if omega is None else omega, mol.alpha if alpha is None else alpha,
                              mol.beta if beta is None else beta, schwarz_tol, precision, terms,
                              1 if autotune else 0, kernel_variant, mixed_tau64, mixed_p64, max_tasks,

@@ -70,6 +70,14 @@ def test_bad_indices_and_exponents(tdg):
     assert e.value.status == tdg.TDG_EINVAL
 
 
+def test_spherical_flag_checked(tdg):
+    m = molecules.make([[0, 0, 0]], [(0, 2, [1.0], [1.0])])
+    m.spherical = 2
+    with pytest.raises(tdg.TdgError) as e:
+        tdg.Plan(m)
+    assert e.value.status == tdg.TDG_EINVAL
+
+
 def test_null_arguments(tdg):
     L = tdg.lib()
     assert L.tdg_plan_create(None, None, 0, None) == tdg.TDG_EINVAL
