@@ -55,3 +55,29 @@ def test_spherical_fock(tdg, oracle_lib):
         e = np.abs(F - ref).max() / np.abs(ref).max()
         _say("spherical Fock", cf, "rel err", e)
         assert e <= 1e-10
+
+
+def test_spherical_batch_noalloc_and_update_coords(tdg, oracle_lib):
+    """The other entry points share the transform: a batch of a spherical and a Cartesian
+    molecule equals single calls; the allocation-free call and a geometry update of a
+    spherical plan equal the oracle."""
+    import torch
+    ms = synth.spherical_copy(molecules.small_mixed(), seed=8)
+    mc = synth.config0()
+    ps, pc = tdg.Plan(ms, schwarz_tol=1e-12), tdg.Plan(mc, schwarz_tol=1e-12)
+    gb = tdg.grad_batch([ps, pc], [(ms.P0, ms.PD, ms.R), (mc.P0, mc.PD, mc.R)])
+    for g, p, m in zip(gb, (ps, pc), (ms, mc)):
+        assert np.abs(g - p.grad(m.P0, m.PD, m.R)).max() <= 1e-12 * max(1.0, np.abs(g).max())
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    out = torch.zeros((ms.n_atoms, 3), dtype=torch.float64, device=dev)
+    ps.grad_device_noalloc(t(ms.P0), t(ms.PD), t(ms.R), out)
+    torch.cuda.synchronize()
+    ref = oracle_lib.grad(ms, tau=1e-12)
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
+    x1 = ms.coords + np.random.default_rng(3).uniform(-0.2, 0.2, ms.coords.shape)
+    ps.update_coords(x1)
+    g1 = ps.grad(ms.P0, ms.PD, ms.R)
+    ref1 = oracle_lib.grad(ms, tau=1e-12, coords=x1)
+    _say("spherical after update_coords: max abs error", np.abs(g1 - ref1).max())
+    assert np.abs(g1 - ref1).max() <= 1e-9 * max(1.0, np.abs(ref1).max())
