@@ -29,6 +29,10 @@ FOCK_CASES = {
     # Fock-type matrix of eq G_2e, (cJ, cK, cKlr) = (2, -alpha, -beta), of the chain's relaxed
     # difference density: blocks of 10 shell pairs (seeded sample, diagonal pair included)
     "chain60_fock_pd": dict(mol=synth.config1, dens="PD", npairs=10, seed=21),
+    # the same for the 120-atom droplet of the at-scale quartet samples (ground-state density),
+    # eight shell pairs
+    "droplet120_fock_p0": dict(mol=lambda: synth.droplet(120, 20240716 + 2 + 1000 * 65), dens="P0", npairs=8,
+                               seed=22),
 }
 
 

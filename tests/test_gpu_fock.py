@@ -174,3 +174,28 @@ def test_fock_chain60_sampled(tdg, oracle_lib):
                     for (a, b), blk in zip(pairs, blocks)) / scale
         _say(f"  tau {tau}: quartets {st['quartets']} kernels {st['ms_kernels']:.1f} ms, rel err {worst:.2e}")
         assert worst <= tol, (tau, worst)
+
+
+def test_fock_droplet120_stored_blocks(tdg):
+    """The 120-atom droplet (1000 functions) of the at-scale quartet samples: eq G_2e of its
+    ground-state density, unscreened (6.7e9 unique quartets) and at tau = 1e-10, against
+    eight shell-pair blocks stored by tests/golden/make_golden.py from the oracle."""
+    import json
+    import os
+    from paper_2407_16586_amd import synth
+    with open(os.path.join(os.path.dirname(__file__), "golden", "droplet120_fock_p0.json")) as fh:
+        gf = json.load(fh)
+    m = synth.droplet(120, 20240716 + 2 + 1000 * 65)
+    assert m.n_bf == gf["n_bf"]
+    B = getattr(m, gf["density"])
+    off, sl = m.shell_ao_off, m.shell_l
+    nc = (sl + 1) * (sl + 2) // 2
+    scale = max(np.abs(np.array(b)).max() for b in gf["blocks"])
+    for tau, tol in ((0.0, REL), (1e-10, 1e-7 / scale)):
+        p = tdg.Plan(m, schwarz_tol=tau)
+        F, st = p.fock(B, *gf["coefs"], stats=True)
+        worst = max(np.abs(F[off[a]:off[a] + nc[a], off[b]:off[b] + nc[b]] - np.array(blk)).max()
+                    for (a, b), blk in zip(gf["pairs"], gf["blocks"])) / scale
+        _say(f"droplet120 tau {tau}: quartets {st['quartets']} kernels {st['ms_kernels']:.1f} ms, rel err {worst:.2e}")
+        assert worst <= tol, (tau, worst)
+        p.close()
