@@ -57,9 +57,11 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *w, const uint1
     if (s < n) out[s] = y;
 }
 
-// loss = mean (pred - y)^2 over the n samples; gradient summed into g.  One wavefront
-// (one block) per 64 samples; the layer inputs are rounded to BF16 exactly where the
-// forward pass rounds them.
+// loss = mean (pred - y)^2 over the n samples; gradient summed into g.  One wavefront per
+// block; a block takes tiles of 64 samples at a grid stride and keeps its partial gradient in
+// registers (each lane holds the matrix-core output elements it produces, and the bias and
+// output-layer sums of its column), so that it adds into g once at the end instead of once
+// per tile.  The layer inputs are rounded to BF16 exactly where the forward pass rounds them.
 __global__ void __launch_bounds__(64) k_mlp_grad(const float *w, const uint16_t *w1b, const uint16_t *w2b,
                                                  const float *X, const float *Y, long long n, float *g, float *loss)
 {
@@ -67,94 +69,134 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float *w, const uint16_t 
     __shared__ uint16_t x[64 * MLP_IN], h1[64 * MLP_H], d2[64 * MLP_H], d1[64 * MLP_H];
     __shared__ float h2[64 * MLP_H], dout[64];
     mlp_load_shared(S, w1b, w2b, w);
-    __syncthreads();
     const int lane = threadIdx.x;
-    const long long s = (long long)blockIdx.x * 64 + lane;
-    const bool ok = s < n;
-#pragma unroll
-    for (int i = 0; i < MLP_IN; ++i) x[lane * MLP_IN + i] = f2bf(ok ? X[s * MLP_IN + i] : 0.f);
-    __syncthreads();
     const int kq = 4 * (lane >> 4), col = lane & 15;
-    for (int mi = 0; mi < 4; ++mi)
-        for (int ni = 0; ni < 4; ++ni) {
-            f32x4 d = mfma_tile([&](int m, int k) { return x[m * MLP_IN + k]; },
-                                [&](int k, int nn) { return S.w1[nn * MLP_IN + k]; }, 16 * mi, 16 * ni, 1, lane);
+    static_assert(MLP_H == 64, "one hidden unit per lane in the bias and output-layer sums");
+    float a_w2[4][4][4], a_w1[4][4], a_w3 = 0.f, a_b2 = 0.f, a_b1 = 0.f, a_b3 = 0.f, a_loss = 0.f;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int m = 16 * mi + kq + t, nn = 16 * ni + col;
-                const float z = d[t] + S.b1[nn];
-                h1[m * MLP_H + nn] = f2bf(z > 0.f ? z : 0.f);
-            }
-        }
-    __syncthreads();
     for (int mi = 0; mi < 4; ++mi)
-        for (int ni = 0; ni < 4; ++ni) {
-            f32x4 d = mfma_tile([&](int m, int k) { return h1[m * MLP_H + k]; },
-                                [&](int k, int nn) { return S.w2[nn * MLP_H + k]; }, 16 * mi, 16 * ni, 4, lane);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int m = 16 * mi + kq + t, nn = 16 * ni + col;
-                const float z = d[t] + S.b2[nn];
-                h2[m * MLP_H + nn] = z > 0.f ? z : 0.f;
+        for (int t = 0; t < 4; ++t) {
+            a_w1[mi][t] = 0.f;
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni) a_w2[mi][ni][t] = 0.f;
+        }
+    for (long long t0 = (long long)blockIdx.x * 64; t0 < n; t0 += (long long)gridDim.x * 64) {
+        __syncthreads(); // the previous tile's reads of x, h1, d1, d2 are done (and S is loaded)
+        const long long s = t0 + lane;
+        const bool ok = s < n;
+#pragma unroll
+        for (int i = 0; i < MLP_IN; ++i) x[lane * MLP_IN + i] = f2bf(ok ? X[s * MLP_IN + i] : 0.f);
+        __syncthreads();
+        for (int mi = 0; mi < 4; ++mi)
+            for (int ni = 0; ni < 4; ++ni) {
+                f32x4 d = mfma_tile([&](int m, int k) { return x[m * MLP_IN + k]; },
+                                    [&](int k, int nn) { return S.w1[nn * MLP_IN + k]; }, 16 * mi, 16 * ni, 1, lane);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int m = 16 * mi + kq + t, nn = 16 * ni + col;
+                    const float z = d[t] + S.b1[nn];
+                    h1[m * MLP_H + nn] = f2bf(z > 0.f ? z : 0.f);
+                }
             }
+        __syncthreads();
+        for (int mi = 0; mi < 4; ++mi)
+            for (int ni = 0; ni < 4; ++ni) {
+                f32x4 d = mfma_tile([&](int m, int k) { return h1[m * MLP_H + k]; },
+                                    [&](int k, int nn) { return S.w2[nn * MLP_H + k]; }, 16 * mi, 16 * ni, 4, lane);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int m = 16 * mi + kq + t, nn = 16 * ni + col;
+                    const float z = d[t] + S.b2[nn];
+                    h2[m * MLP_H + nn] = z > 0.f ? z : 0.f;
+                }
+            }
+        __syncthreads();
+        // output, loss and d loss / d out
+        float o = S.b3;
+        for (int c = 0; c < MLP_H; ++c) o += h2[lane * MLP_H + c] * S.w3[c];
+        const float e = ok ? o - Y[s] : 0.f;
+        dout[lane] = 2.f * e / (float)n;
+        a_loss += e * e / (float)n;
+        __syncthreads();
+        // layer 3 and dz2 (hidden unit c = lane)
+        {
+            const int c = lane;
+            float gw3 = 0.f, gb2 = 0.f;
+            for (int k = 0; k < 64; ++k) {
+                const float hv = h2[k * MLP_H + c];
+                gw3 += dout[k] * hv;
+                const float dz = hv > 0.f ? dout[k] * S.w3[c] : 0.f;
+                d2[k * MLP_H + c] = f2bf(dz);
+                gb2 += dz;
+            }
+            a_w3 += gw3;
+            a_b2 += gb2;
         }
-    __syncthreads();
-    // output, loss and d loss / d out
-    float o = S.b3;
-    for (int c = 0; c < MLP_H; ++c) o += h2[lane * MLP_H + c] * S.w3[c];
-    const float e = ok ? o - Y[s] : 0.f;
-    dout[lane] = 2.f * e / (float)n;
-    float l2 = e * e / (float)n;
-    for (int off = 32; off > 0; off >>= 1) l2 += __shfl_xor(l2, off);
-    if (lane == 0) atomicAdd(loss, l2);
-    __syncthreads();
-    // layer 3 and dz2
-    for (int c = lane; c < MLP_H; c += 64) {
-        float gw3 = 0.f, gb2 = 0.f;
-        for (int k = 0; k < 64; ++k) {
-            const float hv = h2[k * MLP_H + c];
-            gw3 += dout[k] * hv;
-            const float dz = hv > 0.f ? dout[k] * S.w3[c] : 0.f;
-            d2[k * MLP_H + c] = f2bf(dz);
-            gb2 += dz;
+        if (lane == 0) {
+            float gb3 = 0.f;
+            for (int k = 0; k < 64; ++k) gb3 += dout[k];
+            a_b3 += gb3;
         }
-        atomicAdd(&g[MLP_W3 + c], gw3);
-        atomicAdd(&g[MLP_B2 + c], gb2);
+        __syncthreads();
+        // dW2[n][k] = sum_s dz2[s][n] h1[s][k];  dh1[s][k] = sum_n dz2[s][n] W2[n][k]
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni) {
+                f32x4 d = mfma_tile([&](int m, int k) { return d2[k * MLP_H + m]; },
+                                    [&](int k, int nn) { return h1[k * MLP_H + nn]; }, 16 * mi, 16 * ni, 4, lane);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) a_w2[mi][ni][t] += d[t];
+                f32x4 e2 = mfma_tile([&](int m, int k) { return d2[m * MLP_H + k]; },
+                                     [&](int k, int nn) { return S.w2[k * MLP_H + nn]; }, 16 * mi, 16 * ni, 4, lane);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int m = 16 * mi + kq + t, nn = 16 * ni + col;
+                    d1[m * MLP_H + nn] = f2bf(h1[m * MLP_H + nn] != 0 ? e2[t] : 0.f);
+                }
+            }
+        __syncthreads();
+        {
+            float gb1 = 0.f;
+            for (int k = 0; k < 64; ++k) gb1 += bf2f(d1[k * MLP_H + lane]);
+            a_b1 += gb1;
+        }
+        // dW1[n][i] = sum_s dz1[s][n] x[s][i]
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi) {
+            f32x4 d = mfma_tile([&](int m, int k) { return d1[k * MLP_H + m]; },
+                                [&](int k, int nn) { return x[k * MLP_IN + nn]; }, 16 * mi, 0, 4, lane);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) a_w1[mi][t] += d[t];
+        }
     }
+    // one addition per gradient element and block
+    for (int off = 32; off > 0; off >>= 1) a_loss += __shfl_xor(a_loss, off);
     if (lane == 0) {
-        float gb3 = 0.f;
-        for (int k = 0; k < 64; ++k) gb3 += dout[k];
-        atomicAdd(&g[MLP_B3], gb3);
+        atomicAdd(loss, a_loss);
+        atomicAdd(&g[MLP_B3], a_b3);
     }
-    __syncthreads();
-    // dW2[n][k] = sum_s dz2[s][n] h1[s][k];  dh1[s][k] = sum_n dz2[s][n] W2[n][k]
+    atomicAdd(&g[MLP_W3 + lane], a_w3);
+    atomicAdd(&g[MLP_B2 + lane], a_b2);
+    atomicAdd(&g[MLP_B1 + lane], a_b1);
+#pragma unroll
     for (int mi = 0; mi < 4; ++mi)
-        for (int ni = 0; ni < 4; ++ni) {
-            f32x4 d = mfma_tile([&](int m, int k) { return d2[k * MLP_H + m]; },
-                                [&](int k, int nn) { return h1[k * MLP_H + nn]; }, 16 * mi, 16 * ni, 4, lane);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) atomicAdd(&g[MLP_W2 + (16 * mi + kq + t) * MLP_H + 16 * ni + col], d[t]);
-            f32x4 e2 = mfma_tile([&](int m, int k) { return d2[m * MLP_H + k]; },
-                                 [&](int k, int nn) { return S.w2[k * MLP_H + nn]; }, 16 * mi, 16 * ni, 4, lane);
+        for (int t = 0; t < 4; ++t) {
+            atomicAdd(&g[MLP_W1 + (16 * mi + kq + t) * MLP_IN + col], a_w1[mi][t]);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int m = 16 * mi + kq + t, nn = 16 * ni + col;
-                d1[m * MLP_H + nn] = f2bf(h1[m * MLP_H + nn] != 0 ? e2[t] : 0.f);
-            }
+            for (int ni = 0; ni < 4; ++ni)
+                atomicAdd(&g[MLP_W2 + (16 * mi + kq + t) * MLP_H + 16 * ni + col], a_w2[mi][ni][t]);
         }
-    __syncthreads();
-    for (int c = lane; c < MLP_H; c += 64) {
-        float gb1 = 0.f;
-        for (int k = 0; k < 64; ++k) gb1 += bf2f(d1[k * MLP_H + c]);
-        atomicAdd(&g[MLP_B1 + c], gb1);
-    }
-    // dW1[n][i] = sum_s dz1[s][n] x[s][i]
-    for (int mi = 0; mi < 4; ++mi) {
-        f32x4 d = mfma_tile([&](int m, int k) { return d1[k * MLP_H + m]; },
-                            [&](int k, int nn) { return x[k * MLP_IN + nn]; }, 16 * mi, 0, 4, lane);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) atomicAdd(&g[MLP_W1 + (16 * mi + kq + t) * MLP_IN + col], d[t]);
-    }
+}
+
+// blocks of the gradient launch: one per 64-sample tile up to 1024 (tiles beyond that are
+// taken at a grid stride)
+static unsigned mlp_grad_blocks(long long n)
+{
+    const long long tiles = (n + 63) / 64;
+    return (unsigned)(tiles < 1024 ? (tiles > 0 ? tiles : 1) : 1024);
 }
 
 __global__ void k_mlp_adam(float *w, float *m, float *v, float *g, uint16_t *w1b, uint16_t *w2b, float lr, float b1,
@@ -268,7 +310,7 @@ int tdg_mlp_grad(tdg_mlp_t *m, const float *X, const float *Y, int64_t n, float 
     HIPM_TRY(hipSetDevice(m->device));
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, m->loss, 1, 0.f);
-    hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, m->w, m->w1b, m->w2b, X, Y,
+    hipLaunchKernelGGL(k_mlp_grad, dim3(mlp_grad_blocks(n)), dim3(64), 0, st, m->w, m->w1b, m->w2b, X, Y,
                        (long long)n, m->g, m->loss);
     HIPM_TRY(hipGetLastError());
     if (grad_out) {
@@ -287,7 +329,7 @@ int tdg_mlp_train_step(tdg_mlp_t *m, const float *X, const float *Y, int64_t n, 
     HIPM_TRY(hipSetDevice(m->device));
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, m->loss, 1, 0.f);
-    hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, m->w, m->w1b, m->w2b, X, Y,
+    hipLaunchKernelGGL(k_mlp_grad, dim3(mlp_grad_blocks(n)), dim3(64), 0, st, m->w, m->w1b, m->w2b, X, Y,
                        (long long)n, m->g, m->loss);
     m->steps += 1;
     const float b1 = 0.9f, b2 = 0.999f;
