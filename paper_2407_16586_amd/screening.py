@@ -102,9 +102,10 @@ def schwarz_only(mol, ref, tol=1e-6, taus=(1e-7, 3e-8, 1e-8, 3e-9, 1e-9, 3e-10, 
     return None, None, None
 
 
-def budget_threshold(n_quartets, budget=1e-6, margin=1.0):
+def budget_threshold(n_quartets, budget=1e-6, margin=2.0):
     """Veto threshold (log10 of a quartet's largest contribution) from an error budget that
     scales with the system: n vetoed contributions of random sign below t add up to about
     t sqrt(n), so t = budget / sqrt(n), lowered by `margin` decades for the estimator's own
-    error."""
+    error (one decade left the 133-water gradient between 6e-7 and 2.8e-6 from the reference
+    over repeated trainings; two decades)."""
     return float(np.log10(budget) - 0.5 * np.log10(max(n_quartets, 1)) - margin)
