@@ -82,9 +82,10 @@ def test_null_arguments(tdg):
     L = tdg.lib()
     assert L.tdg_plan_create(None, None, 0, None) == tdg.TDG_EINVAL
     assert L.tdg_grad_jk(None, None, None, None, 0, None, None, None) == tdg.TDG_EINVAL
-    assert L.tdg_fock(None, None, 0, None, 1.0, 0.0, 0.0, 0, None, None) == tdg.TDG_EINVAL
     assert L.tdg_plan_destroy(None) == tdg.TDG_OK
     assert b"null" in L.tdg_last_error()
+    assert L.tdg_fock(None, None, 0, None, 1.0, 0.0, 0.0, 0, None, None) == tdg.TDG_EINVAL
+    assert L.tdg_last_error()
 
 
 def test_long_range_needs_omega(tdg):
