@@ -27,7 +27,11 @@ struct WaveClass {
     static constexpr int NBASE = (LA + 1) * (LB + 1) * (LC + 1) * (LD + 1);
     static constexpr int TAB = 12 * NBASE;               // doubles per slot (3 dirs x 4 kinds)
     static constexpr int FB = (int)sizeof(F);
-    static constexpr int CH_LDS = (14 * 1024) / (TAB * FB) > 0 ? (14 * 1024) / (TAB * FB) : 1;
+    // LDS for the root-slot tables of one wavefront: 14 KB, or 40 KB for the classes with
+    // large tables (at least 36 base entries: d on three centres), where 14 KB holds only one
+    // or two slots and leaves stage 1 with a handful of active lanes per chunk
+    static constexpr int TAB_BUDGET = NBASE >= 36 ? 40 * 1024 : 14 * 1024;
+    static constexpr int CH_LDS = TAB_BUDGET / (TAB * FB) > 0 ? TAB_BUDGET / (TAB * FB) : 1;
     static constexpr int CH0 = CH_LDS < NSLOT ? CH_LDS : NSLOT;
     static constexpr int CH = CH0 * 3 <= kWave ? CH0 : kWave / 3;
     static constexpr int NCHUNK = (NSLOT + CH - 1) / CH;
