@@ -14,18 +14,23 @@
  * where P is the ground-state density P0, D = P0 + 2 PDelta, R the TDA
  * transition density, (..|..) the Coulomb ERI of eq eri_j and (..|..)_lr the
  * erf(omega r)/r ERI of eq lreri_k, over contracted Cartesian Gaussians of
- * eq cartG with l <= 2.  The derivative of each quartet follows eqs deri,
+ * eq cartG with l <= 2 (d shells optionally as real solid harmonics, see
+ * tdg_basis_t.spherical).  The derivative of each quartet follows eqs deri,
  * deriv, ti and eriupdate (section II.C); the integrals are evaluated by Rys
  * quadrature in hand-written HIP kernels.  Units: hartree/bohr; the output is
  * dE/dA (the gradient, not the force).
+ *
+ * It also builds the two-electron part of the Fock-type matrices of the
+ * Z-vector equations (section II.B, eqs G_2e and zfock): tdg_fock.
  *
  * Conventions
  *   - Every Cartesian component is normalised to one (primitive, contraction
  *     and angular factor).  Components of a shell are ordered lx descending,
  *     then ly descending: p = x,y,z; d = xx,xy,xz,yy,yz,zz.
  *   - Density matrices are FP64, row-major n_bf x n_bf, in the AO order given
- *     by shell_ao_off.  P0 and PDelta must be symmetric (only their symmetric
- *     part enters); R is general.
+ *     by shell_ao_off (n_bf counts 5 functions per d shell of a spherical basis).
+ *     P0 and PDelta must be symmetric (only their symmetric part enters); R is
+ *     general.
  *   - All entry points return TDG_OK (0) or a negative tdg_status; they never
  *     abort or throw.  tdg_last_error() returns a thread-local message.
  *   - On error no partial result is written to grad.
