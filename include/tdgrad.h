@@ -326,6 +326,8 @@ int tdg_quartet_contribs(tdg_plan_t *plan, const double *P0, const double *PDelt
  * vectors of late Z-vector iterations from being screened away; 0 = absolute.  FP64
  * throughout, whatever the plan's precision.  The class kernels run side by side on the
  * plan's streams as in tdg_grad_jk (joined back into hip_stream before the last step).
+ * The matrix is summed with FP64 atomics, so it is not bitwise repeatable (the plan's
+ * deterministic setting applies to gradients only).
  * stats may be NULL; when given, quartets,
  * prim_quartets, candidates, class_quartets, class_prim_quartets, class_ms (each Fock class
  * kernel timed alone on hip_stream: the call waits after every launch), chunks, ms_kernels
