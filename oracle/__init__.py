@@ -286,6 +286,39 @@ def fock(mol, B, cJ=1.0, cK=0.0, cKlr=0.0, omega=None, nthreads=0):
     return F
 
 
+def cphf_matrix(mol, C_occ, C_vir, omega=None, alpha=None, beta=None):
+    """A of eq cphf_a (section II.B) without the exchange-correlation kernel term, written out
+    from its definition in the molecular orbitals:
+      A_{ai,bj} = 4 (ia|jb) - alpha [(ij|ab) + (ib|aj)] - beta [(ij|ab)_lr + (ib|aj)_lr],
+    rows (a, i) and columns (b, j) in row-major (virtual, occupied) order."""
+    al = mol.alpha if alpha is None else alpha
+    be = mol.beta if beta is None else beta
+    Co, Cv = np.asarray(C_occ, dtype=np.float64), np.asarray(C_vir, dtype=np.float64)
+
+    def mo(T, X1, X2, X3, X4):
+        return np.einsum("pqrs,pi,qj,rk,sl->ijkl", T, X1, X2, X3, X4, optimize=True)
+
+    I = eri_tensor(mol, 0)
+    Il = eri_tensor(mol, 1, omega)
+    ovov = lambda T: mo(T, Co, Cv, Co, Cv)      # (ia|jb)[i, a, j, b]
+    oovv = lambda T: mo(T, Co, Co, Cv, Cv)      # (ij|ab)[i, j, a, b]
+    ovvo = lambda T: mo(T, Co, Cv, Cv, Co)      # (ib|aj)[i, b, a, j]
+    A = (4.0 * np.einsum("iajb->aibj", ovov(I))
+         - al * (np.einsum("ijab->aibj", oovv(I)) + np.einsum("ibaj->aibj", ovvo(I)))
+         - be * (np.einsum("ijab->aibj", oovv(Il)) + np.einsum("ibaj->aibj", ovvo(Il))))
+    no, nv = Co.shape[1], Cv.shape[1]
+    return A.reshape(nv * no, nv * no)
+
+
+def zvector(mol, C_occ, C_vir, eps_occ, eps_vir, L, omega=None, alpha=None, beta=None):
+    """Z of eq cphf, (d - A) Z = L with d_ai = eps_i - eps_a, by a direct dense solve."""
+    A = cphf_matrix(mol, C_occ, C_vir, omega, alpha, beta)
+    eo, ev = np.asarray(eps_occ), np.asarray(eps_vir)
+    d = (eo[None, :] - ev[:, None]).reshape(-1)
+    Z = np.linalg.solve(np.diag(d) - A, np.asarray(L, dtype=np.float64).reshape(-1))
+    return Z.reshape(len(ev), len(eo))
+
+
 def schwarz(mol):
     bb = _Bound(mol)
     ns = mol.n_shells
