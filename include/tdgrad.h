@@ -338,6 +338,25 @@ int tdg_quartet_contribs(tdg_plan_t *plan, const double *P0, const double *PDelt
 int tdg_fock(tdg_plan_t *plan, const double *B, int32_t ptr_kind, void *hip_stream, double cJ,
              double cK, double cKlr, int32_t relative, double *F, tdg_stats_t *stats);
 
+/* Z-vector (coupled-perturbed) equations of section II.B, eq cphf: (d - A) Z = L with
+ * d_ai = eps_i - eps_a and A of eq cphf_a without its exchange-correlation kernel term,
+ * solved by the Krylov subspace method of the same section: b0 = d^-1 L, orthonormal
+ * subspace vectors (each normalised before its Fock build), the products
+ * A b = C_v^T F(C_v b C_o^T) C_o of eqs sigma and zfock with F = tdg_fock(B; cJ, cK, cKlr,
+ * relative) -- eq zfock is (cJ, cK, cKlr) = (4, -2 alpha, -2 beta) -- and the subspace
+ * equations (delta_ij - b_i . d^-1 A b_j) a_j = delta_i0 |b0| solved on the host, until
+ * |d^-1 L - (I - d^-1 A) Z| <= tol |d^-1 L| or max_iter products.
+ * C_occ [n_bf][n_occ], C_vir [n_bf][n_vir]: orbital coefficients in the plan's functions,
+ * row-major; eps_occ [n_occ], eps_vir [n_vir] with every occupied energy below every virtual
+ * one; L, Z [n_vir][n_occ] row-major.  Host pointers; synchronous (the plan's device, its
+ * default stream); *iterations = products evaluated, *residual = the final relative
+ * residual (either may be NULL).  Errors: TDG_EINVAL, TDG_ENOMEM, TDG_EDEVICE, TDG_ESTATE
+ * (singular subspace matrix). */
+int tdg_zvector(tdg_plan_t *plan, int32_t n_occ, int32_t n_vir, const double *C_occ,
+                const double *C_vir, const double *eps_occ, const double *eps_vir, const double *L,
+                double cJ, double cK, double cKlr, int32_t relative, double tol, int32_t max_iter,
+                double *Z, int32_t *iterations, double *residual);
+
 /* Release a plan and its device memory (NULL is accepted). */
 int tdg_plan_destroy(tdg_plan_t *plan);
 

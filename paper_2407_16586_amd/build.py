@@ -35,6 +35,7 @@ _DEPS = {
     "tdgrad": ["tdgrad.hip", "class_launch.hpp", "deriv_kernel.hpp", "fock_kernel.hpp", "fock_launch.hpp", "mlp.hpp",
                "../../include/tdgrad.h"] + _DEV,
     "mlp": ["mlp.hip", "mlp.hpp", "../../include/tdgrad.h"],
+    "zvector": ["zvector.hip", "../../include/tdgrad.h"],
     "class": ["class_kernels.hip", "class_launch.hpp", "deriv_kernel.hpp", "deriv_wave.hpp"] + _DEV,
     "fock": ["fock_kernels.hip", "fock_launch.hpp", "fock_kernel.hpp", "deriv_kernel.hpp"] + _DEV,
 }
@@ -56,7 +57,8 @@ def build(extra_flags: list[str] | None = None, verbose: bool = False, jobs: int
         odir = os.path.join(os.path.dirname(CSRC), "_build") if incremental else tmpd
         os.makedirs(odir, exist_ok=True)
         jobs_ = [(MAIN, os.path.join(odir, "tdgrad.o"), [], "tdgrad"),
-                 (os.path.join(CSRC, "mlp.hip"), os.path.join(odir, "mlp.o"), [], "mlp")]
+                 (os.path.join(CSRC, "mlp.hip"), os.path.join(odir, "mlp.o"), [], "mlp"),
+                 (os.path.join(CSRC, "zvector.hip"), os.path.join(odir, "zvector.o"), [], "zvector")]
         for c in range(NUM_CLASSES):
             jobs_.append((CLASS_SRC, os.path.join(odir, f"class_{c}.o"), [f"-DTDG_CLASS={c}"], "class"))
         for c in range(NUM_CLASSES):

@@ -51,6 +51,8 @@ static int fail(int code, const char *fmt, ...)
 }
 
 extern "C" int tdg_set_error_(int code, const char *msg) { return fail(code, "%s", msg); }
+struct tdg_plan;
+int tdg_plan_device_(const tdg_plan *pl); // the plan's HIP device (for zvector.hip)
 
 namespace tdg {
 void mlp_device_ptrs(const tdg_mlp *m, const float **w, const uint16_t **w1b, const uint16_t **w2b);
@@ -1376,6 +1378,10 @@ int tdg_plan_destroy(tdg_plan_t *pl)
     delete pl;
     return TDG_OK;
 }
+
+} // extern "C"
+int tdg_plan_device_(const tdg_plan *pl) { return pl->device; }
+extern "C" {
 
 int tdg_plan_set_streams(tdg_plan_t *pl, int32_t streams)
 {

@@ -24,7 +24,7 @@ CLASSES = tuple(PAIR_CLASSES[b] + PAIR_CLASSES[k] for b in range(6) for k in ran
 EXPORTED = ("tdg_plan_create", "tdg_grad_jk", "tdg_grad_jk_batch", "tdg_plan_destroy", "tdg_plan_dims",
             "tdg_plan_schwarz", "tdg_rys_rule", "tdg_plan_set_screen_model", "tdg_collect",
             "tdg_plan_update_coords", "tdg_screen_list", "tdg_quartet_contribs", "tdg_grad_jk_noalloc", "tdg_plan_set_streams",
-            "tdg_fock",
+            "tdg_fock", "tdg_zvector",
             "tdg_mlp_create", "tdg_mlp_destroy", "tdg_mlp_nweights", "tdg_mlp_set_weights",
             "tdg_mlp_get_weights", "tdg_mlp_forward", "tdg_mlp_grad", "tdg_mlp_train_step",
             "tdg_last_error")
@@ -108,6 +108,9 @@ def lib():
         L.tdg_quartet_contribs.argtypes = [vp, vp, vp, vp, C.c_int32, vp, C.c_int64, vp, C.c_int32, vp]
         L.tdg_fock.argtypes = [vp, vp, C.c_int32, vp, C.c_double, C.c_double, C.c_double, C.c_int32, vp,
                                C.POINTER(Stats)]
+        L.tdg_zvector.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, vp, vp, C.c_double, C.c_double,
+                                  C.c_double, C.c_int32, C.c_double, C.c_int32, vp, C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_double)]
         L.tdg_mlp_create.argtypes = [C.c_int, C.c_uint64, C.POINTER(vp)]
         L.tdg_mlp_destroy.argtypes = [vp]
         L.tdg_mlp_nweights.argtypes = []
@@ -251,6 +254,25 @@ class Plan:
         _check(lib().tdg_fock(self._h, B.data_ptr(), 1, s, float(cJ), float(cK), float(cKlr), int(bool(relative)),
                               out.data_ptr(), C.byref(st) if stats else None))
         return st.as_dict() if stats else None
+
+    def zvector(self, C_occ, C_vir, eps_occ, eps_vir, L, cJ=4.0, cK=None, cKlr=None, relative=True, tol=1e-10,
+                max_iter=50):
+        """Z of (d - A) Z = L (tdg_zvector; host numpy arrays); returns (Z [n_vir, n_occ],
+        products evaluated, final relative residual).  cK, cKlr default to eq zfock's
+        -2 alpha and -2 beta of the plan's parameters."""
+        c = lambda x: np.ascontiguousarray(x, dtype=np.float64)
+        Co, Cv, eo, ev, Lm = c(C_occ), c(C_vir), c(eps_occ), c(eps_vir), c(L)
+        no, nv = Co.shape[1], Cv.shape[1]
+        if Co.shape[0] != self.n_bf or Cv.shape[0] != self.n_bf or Lm.shape != (nv, no):
+            raise ValueError("shape mismatch")
+        cK = -2.0 * self.params.alpha if cK is None else cK
+        cKlr = -2.0 * self.params.beta if cKlr is None else cKlr
+        Z = np.zeros((nv, no))
+        it, res = C.c_int32(), C.c_double()
+        _check(lib().tdg_zvector(self._h, no, nv, _ptr(Co), _ptr(Cv), _ptr(eo), _ptr(ev), _ptr(Lm), float(cJ),
+                                 float(cK), float(cKlr), int(bool(relative)), float(tol), int(max_iter), _ptr(Z),
+                                 C.byref(it), C.byref(res)))
+        return Z, it.value, res.value
 
     def set_screen_model(self, model, log10_threshold=-12.0, tau_hi=1e-6):
         """Attach a trained Estimator (or None); it vetoes quartets after the Schwarz
